@@ -1,0 +1,189 @@
+/*
+ * open.h -- C ABI of the MI355X collaborative-filtering hot path of OPEN
+ * (online performance prediction under CPU and GPU power caps).
+ *
+ * The paper completes a sparse application x power-setting performance matrix from a few
+ * profiled entries of each new application (Section III-B.1 and III-B.2; the matrix of
+ * Eq. 1 gains one sparse row per new application) and then picks the energy-efficient
+ * CPU/GPU cap pair of each application with Algorithm 2 (Section III-B.3).  This library
+ * completes the matrix by weighted-lambda alternating least squares (the CF formulation
+ * of the paper's Netflix-prize reference, Zhou et al. 2008, cited in Section III-B.1),
+ * folds new rows in against fixed setting factors, predicts, and selects.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major float32; rows are applications, columns are settings.
+ *     A setting index is s = a * n_gpu + b for CPU-cap index a and GPU-cap index b.
+ *   - Sparse inputs are CSR: row_ptr int64[m+1] (row_ptr[0] = 0), col int32[nnz] sorted and
+ *     unique within each row and in [0, n), val float32[nnz].
+ *   - Unless stated otherwise every pointer is a DEVICE pointer owned by the caller.  The
+ *     library never frees caller memory and never returns memory it allocated; its own
+ *     workspaces live in the context and are reused across calls.
+ *   - Calls are asynchronous on the context's stream unless they return a host value.
+ *   - Invalid arguments return OPEN_E_INVALID before any work is queued; the message is
+ *     available from open_last_error().  No C++ exception crosses this interface.
+ *   - Per-row numerical failures do not abort a call: the row's output is zero, its
+ *     row_status entry is set and the call returns OPEN_OK; callers inspect row_status.
+ *   - Supported ranks k: 8, 16, 32, 64.  Other ranks return OPEN_E_UNSUPPORTED.
+ *   - One context serves one host thread at a time.  Results are deterministic: repeated
+ *     calls on the same inputs return bitwise identical outputs.
+ */
+#ifndef OPEN_H
+#define OPEN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct open_ctx open_ctx;
+typedef struct open_mlp open_mlp;
+
+typedef enum {
+  OPEN_OK = 0,
+  OPEN_E_INVALID = -1,     /* bad shape, pointer, option or rank */
+  OPEN_E_NOMEM = -2,       /* a workspace allocation failed */
+  OPEN_E_DEVICE = -3,      /* a HIP runtime call failed */
+  OPEN_E_UNSUPPORTED = -4  /* valid request this build does not implement (e.g. rank 12) */
+} open_status;
+
+/* row_status values */
+enum {
+  OPEN_ROW_OK = 0,
+  OPEN_ROW_EMPTY = 1,         /* no observed entry: output row is zero */
+  OPEN_ROW_NONPOS_PIVOT = 2,  /* system not positive definite in float32 (e.g. lambda = 0) */
+  OPEN_ROW_NONFINITE = 3,     /* an observed value is NaN or infinite */
+  OPEN_ROW_NONPOS_BASE = 4,   /* Alg. 2: predicted baseline performance not positive */
+  OPEN_ROW_BADINDEX = 5       /* a column index outside [0, n): output row is zero */
+};
+
+/* Context on `device` (HIP ordinal), issuing work on `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  On success *ctx owns the device workspaces until open_destroy. */
+open_status open_create(open_ctx **ctx, int device, void *hip_stream);
+open_status open_destroy(open_ctx *ctx);
+/* Rebind the context to another stream of the same device. */
+open_status open_set_stream(open_ctx *ctx, void *hip_stream);
+/* Last error message of the context (static storage owned by the context; never NULL). */
+const char *open_last_error(const open_ctx *ctx);
+/* Block until the context's stream has drained. */
+open_status open_sync(open_ctx *ctx);
+
+/*
+ * Fold-in (Section III-B.2: a new application's few profiled entries become a sparse row
+ * whose missing entries collaborative filtering fills).  With the setting factors F (n x k)
+ * fixed, every CSR row i (m rows) gets the ridge solution
+ *     u_i = (sum_{j in O_i} f_j f_j^T + lambda w_i I)^-1  sum_{j in O_i} r_ij f_j,
+ * w_i = |O_i| when weighted != 0 (ALS-WR weighting) and 1 otherwise.  The same call is the
+ * row half-sweep of ALS (F = V, rows = applications) and the column half-sweep (F = U, the
+ * CSR being the column view of the matrix).  Rows with |O_i| <= min(k, 32) are solved in the
+ * dual form u = F_O^T (F_O F_O^T + lambda w I)^-1 r, the same number.
+ *   F          device float32[n*k]
+ *   U_out      device float32[m*k], written
+ *   row_status device int32[m] or NULL
+ * lambda must be >= 0 and finite. */
+open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m, const int64_t *row_ptr,
+                        const int32_t *col, const float *val, float lambda, int32_t weighted, float *U_out,
+                        int32_t *row_status);
+
+/*
+ * Column view of a CSR matrix (m x n): col_ptr int64[n+1], row_idx int32[nnz] and
+ * cval float32[nnz], entries ordered by column and, within a column, by row.  Exact
+ * integer work (a stable counting sort).  All pointers are device pointers.
+ */
+open_status open_csr_to_csc(open_ctx *ctx, int64_t m, int32_t n, const int64_t *row_ptr, const int32_t *col,
+                            const float *val, int64_t *col_ptr, int32_t *row_idx, float *cval);
+
+/*
+ * ALS-WR fit (weighted-lambda alternating least squares): `sweeps` times, every row against
+ * V (open_foldin on the CSR), then every column against U (open_foldin on the column view).
+ * A column with no observation gets v_j = 0.  U (m*k) and V (n*k) hold the initial factors
+ * on entry and the fitted factors on return.  obj_hist, when not NULL, is a HOST array of
+ * 2*sweeps doubles receiving the objective
+ *     f = sum_O (r_ij - u_i.v_j)^2 + lambda (sum_i w_i |u_i|^2 + sum_j w^j |v_j|^2)
+ * after every half-sweep; it makes the call synchronous.
+ */
+open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64_t *row_ptr, const int32_t *col,
+                     const float *val, float lambda, int32_t weighted, int32_t sweeps, float *U, float *V,
+                     double *obj_hist);
+
+/* Objective f(U, V) above, reduced in float64 in a fixed order; *out is a HOST double.
+ * Synchronous. */
+open_status open_objective(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64_t *row_ptr,
+                           const int32_t *col, const float *val, const float *U, const float *V, float lambda,
+                           int32_t weighted, double *out);
+
+/* Observed-entry RMS residual of every row, rho_i = sqrt(mean_{j in O_i} (r_ij - u_i.v_j)^2)
+ * (0 for an empty row).  rho: device float32[m]. */
+open_status open_residual(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64_t *row_ptr,
+                          const int32_t *col, const float *val, const float *U, const float *V, float *rho);
+
+/*
+ * Fused predict + Algorithm 2 (Section III-B.3).  p_is = u_i . v_s for all s; with the
+ * baseline setting `base` = (C_b, G_b), E_base = C_b + G_b; setting s is valid when p_is > 0
+ * and 1 - p_is / p_ib <= gamma; its energy bound is E_s = (c_s + g_s) / p_is; the valid
+ * setting of least E_s (greatest saving (E_base - E_s) / E_base) wins, the lowest s on ties.
+ *   U          device float32[m*k];  V device float32[n*k]
+ *   cap_cpu, cap_gpu  device float32[n], watts of setting s
+ *   P          device float32[m*n] or NULL (the full prediction is only written when asked)
+ *   best_idx   device int32[m]; best_saving device float32[m] or NULL
+ *   row_status device int32[m] or NULL (OPEN_ROW_NONPOS_BASE when p_ib <= 0; then
+ *              best_idx = base and saving = 0)
+ */
+open_status open_predict(open_ctx *ctx, const float *U, int64_t m, const float *V, int32_t n, int32_t k, float *P,
+                         const float *cap_cpu, const float *cap_gpu, int32_t base, float gamma, int32_t *best_idx,
+                         float *best_saving, int32_t *row_status);
+
+/*
+ * Fold-in surrogate: a network that maps a new application's masked profile vector
+ * x = [r * mask ; mask] (length 2n) straight to its latent row,
+ *     h1 = GELU(W1 x + b1),  h2 = GELU(W2 h1 + b2),  u = W3 h2 + b3,
+ * GELU(z) = z/2 (1 + erf(z/sqrt 2)), trained on ridge fold-ins and backed by them: a row
+ * whose observed-entry RMS residual exceeds tau is re-solved by open_foldin.  Weights are
+ * kept in float32 (the master copy Adam updates) and used as bfloat16 (round to nearest
+ * even) in the matrix products, which accumulate in float32.
+ *
+ * Parameter packing (host float32 arrays, this order, row-major):
+ *   W1[hidden][2n], b1[hidden], W2[hidden][hidden], b2[hidden], W3[k][hidden], b3[k].
+ * hidden must be 256; n at most 4096.
+ */
+open_status open_mlp_create(open_ctx *ctx, open_mlp **mlp, int32_t n, int32_t k, int32_t hidden,
+                            const float *init_host);
+open_status open_mlp_destroy(open_mlp *mlp);
+/* Number of float32 parameters in the packing above. */
+int64_t open_mlp_num_params(int32_t n, int32_t k, int32_t hidden);
+/* Copy the float32 master weights to a HOST array (packing above).  Synchronous. */
+open_status open_mlp_get_weights(open_mlp *mlp, float *host_out);
+/* Replace the master weights from a HOST array; resets the Adam state and step count. */
+open_status open_mlp_set_weights(open_mlp *mlp, const float *host_in);
+
+/* Network output for every CSR row: U_hat device float32[m*k]. */
+open_status open_mlp_forward(open_mlp *mlp, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                             const float *val, float *U_hat);
+
+/* Loss L = 1/(B k) sum |u_hat_i - target_i|^2 over the B = m rows of the CSR and its gradient
+ * with respect to every parameter (packing above), written to the HOST arrays *loss and
+ * grads_host.  Does not update the weights.  Synchronous.  m <= 16384. */
+open_status open_mlp_loss_grad(open_mlp *mlp, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                               const float *val, const float *target, double *loss, float *grads_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the batch formed by
+ * the CSR rows listed in rows[0..batch) (device int64; NULL = rows 0..batch-1) with targets
+ * target[rows[b]*k ..].  loss_out: device float32 scalar or NULL.  m is the CSR row count. */
+open_status open_mlp_train_step(open_mlp *mlp, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                                const float *val, const float *target, const int64_t *rows, int32_t batch,
+                                float lr, float *loss_out);
+
+/* Surrogate fold-in with ridge fallback: u_i = network output unless its observed-entry RMS
+ * residual against the setting factors F exceeds tau, in which case u_i is the ridge
+ * solution of open_foldin (lambda, weighted).  used_fallback (device uint8[m] or NULL)
+ * marks re-solved rows; rho (device float32[m] or NULL) receives the network's residual;
+ * n_fallback (HOST int64, or NULL) receives the number of re-solved rows and makes the
+ * call synchronous. */
+open_status open_mlp_foldin(open_mlp *mlp, const float *F, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                            const float *val, float tau, float lambda, int32_t weighted, float *U_out,
+                            uint8_t *used_fallback, float *rho, int64_t *n_fallback);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPEN_H */

@@ -1,0 +1,147 @@
+// C ABI entry points of libopen: argument validation, context and workspace management,
+// dispatch to the kernels.  See include/open.h for the contract of every call.
+#include <limits.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "common.h"
+
+namespace openk {
+
+open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out) {
+  if (bytes == 0) bytes = 16;
+  if (ctx->ws_bytes[slot] < bytes) {
+    if (ctx->ws[slot]) {
+      // the stream may still use the old buffer: drain before releasing it
+      OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      OPEN_HIP_TRY(ctx, hipFree(ctx->ws[slot]));
+      ctx->ws[slot] = nullptr;
+      ctx->ws_bytes[slot] = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&ctx->ws[slot], want) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->ws[slot] = nullptr;
+      return fail(ctx, OPEN_E_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    ctx->ws_bytes[slot] = want;
+  }
+  *out = ctx->ws[slot];
+  return OPEN_OK;
+}
+
+open_status pinned_get(open_ctx *ctx, size_t bytes, void **out) {
+  if (ctx->host_pinned_bytes < bytes) {
+    if (ctx->host_pinned) {
+      OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      OPEN_HIP_TRY(ctx, hipHostFree(ctx->host_pinned));
+      ctx->host_pinned = nullptr;
+      ctx->host_pinned_bytes = 0;
+    }
+    OPEN_HIP_TRY(ctx, hipHostMalloc(&ctx->host_pinned, bytes, hipHostMallocDefault));
+    ctx->host_pinned_bytes = bytes;
+  }
+  *out = ctx->host_pinned;
+  return OPEN_OK;
+}
+
+static bool rank_ok(int k) { return k == 8 || k == 16 || k == 32 || k == 64; }
+
+// Validate a CSR header shared by several calls.
+static open_status check_csr(open_ctx *ctx, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                             const float *val) {
+  if (m < 0 || m >= INT_MAX) return fail(ctx, OPEN_E_INVALID, "row count must be in [0, 2^31 - 1)");
+  if (m > 0 && (!row_ptr || !col || !val)) return fail(ctx, OPEN_E_INVALID, "CSR pointers must not be NULL");
+  return OPEN_OK;
+}
+
+}  // namespace openk
+
+using namespace openk;
+
+extern "C" {
+
+open_status open_create(open_ctx **out, int device, void *hip_stream) {
+  if (!out) return OPEN_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return OPEN_E_DEVICE;
+  }
+  open_ctx *ctx = new (std::nothrow) open_ctx();
+  if (!ctx) return OPEN_E_NOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return OPEN_E_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->num_cu = prop.multiProcessorCount;
+  *out = ctx;
+  return OPEN_OK;
+}
+
+open_status open_destroy(open_ctx *ctx) {
+  if (!ctx) return OPEN_E_INVALID;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int i = 0; i < open_ctx::WS_COUNT; ++i)
+    if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
+  if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  delete ctx;
+  return OPEN_OK;
+}
+
+open_status open_set_stream(open_ctx *ctx, void *hip_stream) {
+  if (!ctx) return OPEN_E_INVALID;
+  ctx->stream = (hipStream_t)hip_stream;
+  return OPEN_OK;
+}
+
+const char *open_last_error(const open_ctx *ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+open_status open_sync(open_ctx *ctx) {
+  if (!ctx) return OPEN_E_INVALID;
+  OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return OPEN_OK;
+}
+
+open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m, const int64_t *row_ptr,
+                        const int32_t *col, const float *val, float lambda, int32_t weighted, float *U_out,
+                        int32_t *row_status) {
+  if (!ctx) return OPEN_E_INVALID;
+  if (!rank_ok(k)) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
+  if (n <= 0 || !F) return fail(ctx, OPEN_E_INVALID, "factor matrix must be non-empty");
+  if (!(lambda >= 0.0f) || !isfinite(lambda)) return fail(ctx, OPEN_E_INVALID, "lambda must be finite and >= 0");
+  open_status st = check_csr(ctx, m, row_ptr, col, val);
+  if (st) return st;
+  if (m > 0 && !U_out) return fail(ctx, OPEN_E_INVALID, "output must not be NULL");
+  if (m == 0) return OPEN_OK;
+  OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int32_t *list;
+  int64_t *cls;
+  if ((st = bucket_rows(ctx, m, row_ptr, k, &list, &cls, INT64_MAX))) return st;
+  if (k == 64) {
+    // rank 64 solves only the dual form (n_i <= 32) in this build
+    int64_t *h;
+    if ((st = pinned_get(ctx, sizeof(int64_t) * 2 * kNumClasses, (void **)&h))) return st;
+    OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, cls, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToHost, ctx->stream));
+    OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    int64_t big = 0;
+    for (int c = 9; c < kNumClasses; ++c) big += h[2 * c + 1];
+    if (big) return fail(ctx, OPEN_E_UNSUPPORTED, "rank 64 with more than 32 observed entries in a row");
+  }
+  return rowsolve_launch(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m);
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Row bucketing for the batched ridge solves (fold-in, ALS half-sweeps).
+//
+// Every row is put in a size class by its observed count n_i, and the row ids are
+// written class by class (ascending within a class) by a stable counting sort:
+//   class 0              empty rows
+//   classes 1..8         dual form, system dimension padded to 4*class (n_i <= min(k, 32))
+//   classes 9..15        primal form (k x k system), n_i in (k 2^p, k 2^(p+1)], p = class - 9
+//   class 16             rows long enough for the split-K path
+// Exact integer work; the resulting list is independent of scheduling.
+#include "common.h"
+
+namespace openk {
+
+__global__ void k_fill_i32(int *p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+constexpr int kRowsPerBlock = 1024;
+constexpr int kBucketThreads = 256;
+
+__device__ __forceinline__ int row_class(int64_t cnt, int k, int64_t split_min) {
+  if (cnt <= 0) return 0;
+  const int dmax = k < 32 ? k : 32;
+  if (cnt <= dmax) return (int)((cnt + 3) >> 2);
+  if (cnt >= split_min) return kSplitClass;
+  const int64_t r = (cnt - 1) / k;  // >= 1 here
+  int p = 63 - __clzll((unsigned long long)r);
+  p = p > 6 ? 6 : p;
+  return 9 + p;
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_class_count(int64_t m, const int64_t *__restrict__ ptr, int k,
+                                                                int64_t split_min, int32_t *__restrict__ hist) {
+  __shared__ int h[kNumClasses];
+  if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock;
+  for (int r = threadIdx.x; r < kRowsPerBlock; r += kBucketThreads) {
+    const int64_t i = base + r;
+    if (i < m) atomicAdd(&h[row_class(ptr[i + 1] - ptr[i], k, split_min)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumClasses) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of the class-major histogram (one block); cls[2c] = start, cls[2c+1] = count.
+__global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist, int nblk, int64_t m,
+                                                     int64_t *__restrict__ cls) {
+  __shared__ int64_t part[1024];
+  const int total = kNumClasses * nblk;
+  const int per = (total + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  const int b1 = b0 + per < total ? b0 + per : total;
+  int64_t s = 0;
+  for (int i = b0; i < b1; ++i) s += hist[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+  for (int i = b0; i < b1; ++i) {
+    const int64_t h = hist[i];
+    hist[i] = (int32_t)run;
+    run += h;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumClasses) {
+    const int c = threadIdx.x;
+    const int64_t start = hist[(int64_t)c * nblk];
+    const int64_t end = c + 1 < kNumClasses ? (int64_t)hist[(int64_t)(c + 1) * nblk] : m;
+    cls[2 * c] = start;
+    cls[2 * c + 1] = end - start;
+  }
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const int64_t *__restrict__ ptr, int k,
+                                                                int64_t split_min, const int32_t *__restrict__ offs,
+                                                                int32_t *__restrict__ list) {
+  __shared__ int wcnt[kBucketThreads / kWave][kNumClasses];
+  __shared__ int run[kNumClasses];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid < kNumClasses) run[tid] = offs[(int64_t)tid * gridDim.x + blockIdx.x];
+  __syncthreads();
+  for (int pass = 0; pass < kRowsPerBlock / kBucketThreads; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + pass * kBucketThreads + tid;
+    const int c = i < m ? row_class(ptr[i + 1] - ptr[i], k, split_min) : -1;
+    int rank = 0;
+    for (int cc = 0; cc < kNumClasses; ++cc) {
+      const unsigned long long mask = __ballot(c == cc);
+      if (c == cc) rank = __popcll(mask & ((1ull << lane) - 1ull));
+      if (lane == 0) wcnt[w][cc] = __popcll(mask);
+    }
+    __syncthreads();
+    if (c >= 0) {
+      int pos = run[c];
+      for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][c];
+      list[pos + rank] = (int32_t)i;
+    }
+    __syncthreads();
+    if (tid < kNumClasses) {
+      int add = 0;
+      for (int ww = 0; ww < kBucketThreads / kWave; ++ww) add += wcnt[ww][tid];
+      run[tid] += add;
+    }
+    __syncthreads();
+  }
+}
+
+open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t **list, int64_t **cls,
+                        int64_t split_min) {
+  const int nblk = (int)((m + kRowsPerBlock - 1) / kRowsPerBlock);
+  void *hist = nullptr, *lst = nullptr, *c = nullptr;
+  open_status st;
+  if ((st = ws_get(ctx, open_ctx::WS_HIST, sizeof(int32_t) * (size_t)kNumClasses * (nblk > 0 ? nblk : 1), &hist)))
+    return st;
+  if ((st = ws_get(ctx, open_ctx::WS_LIST, sizeof(int32_t) * (size_t)(m > 0 ? m : 1), &lst))) return st;
+  if ((st = ws_get(ctx, open_ctx::WS_CLS, sizeof(int64_t) * 2 * kNumClasses, &c))) return st;
+  if (m > 0) {
+    hipLaunchKernelGGL(k_class_count, dim3(nblk), dim3(kBucketThreads), 0, ctx->stream, m, row_ptr, k, split_min,
+                       (int32_t *)hist);
+    OPEN_LAUNCH_CHECK(ctx);
+  }
+  hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, ctx->stream, (int32_t *)hist, nblk, m, (int64_t *)c);
+  OPEN_LAUNCH_CHECK(ctx);
+  if (m > 0) {
+    hipLaunchKernelGGL(k_class_place, dim3(nblk), dim3(kBucketThreads), 0, ctx->stream, m, row_ptr, k, split_min,
+                       (const int32_t *)hist, (int32_t *)lst);
+    OPEN_LAUNCH_CHECK(ctx);
+  }
+  *list = (int32_t *)lst;
+  *cls = (int64_t *)c;
+  return OPEN_OK;
+}
+
+}  // namespace openk

@@ -1,0 +1,143 @@
+// Internal helpers shared by the HIP sources of libopen (device intrinsics, launch checks,
+// the context structure).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <type_traits>
+
+#include "../../include/open.h"
+
+namespace openk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- quad (4-lane) exchange
+// DPP quad_perm: every lane of a quad reads lane `src` of its own quad.
+__device__ __forceinline__ float quad_bcast(float x, int src) {
+  switch (src) {
+    case 0: return __builtin_amdgcn_update_dpp(0.0f, x, 0x00, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_update_dpp(0.0f, x, 0x55, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(0.0f, x, 0xaa, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_update_dpp(0.0f, x, 0xff, 0xf, 0xf, false);
+  }
+}
+template <int SRC>
+__device__ __forceinline__ float quad_bcast_c(float x) {
+  return __builtin_amdgcn_update_dpp(0.0f, x, SRC * 0x55, 0xf, 0xf, false);
+}
+// partner lane q^1 and q^2 within the quad
+__device__ __forceinline__ float quad_xor1(float x) {
+  return __builtin_amdgcn_update_dpp(0.0f, x, 0xb1, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float quad_xor2(float x) {
+  return __builtin_amdgcn_update_dpp(0.0f, x, 0x4e, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int quad_xor1_i(int x) { return __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false); }
+__device__ __forceinline__ int quad_xor2_i(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false); }
+
+// 16 independent 4x4 outer products: lanes 4b..4b+3 form block b; block b accumulates
+// D_b[i][j] += A_b[i] * B_b[j] with A_b[i] from lane 4b+i and B_b[j] from lane 4b+j.
+// Result layout: lane 4b+j holds column j of block b, register v = row v.
+__device__ __forceinline__ f4 mfma4x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    int y = __shfl_xor(x, off, kWave);
+    x = x > y ? x : y;
+  }
+  return x;
+}
+
+// fill an int32 array with a value (used instead of memset so the work can sit in a graph)
+__global__ void k_fill_i32(int *p, int64_t n, int v);
+
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // tile (i >= j)
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1 (E > B), or descending
+// for sfor_down<B, E>: i = E-1 .. B.  Indices are constants at the source level, so they can
+// select registers and DPP controls.
+template <int B, int E, class Fn>
+__device__ __forceinline__ void sfor(Fn &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+template <int B, int E, class Fn>
+__device__ __forceinline__ void sfor_down(Fn &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, E - 1>{});
+    sfor_down<B, E - 1>(f);
+  }
+}
+
+}  // namespace openk
+
+// ---------------------------------------------------------------- context
+struct open_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  std::string err;
+  // grow-only device workspaces, indexed by purpose
+  enum {
+    WS_HIST, WS_CLS, WS_LIST, WS_CSC_PTR, WS_CSC_IDX, WS_CSC_VAL, WS_RED, WS_SPLIT, WS_MISC, WS_FLAG, WS_OBJ,
+    WS_PRED, WS_COUNT
+  };
+  void *ws[WS_COUNT] = {};
+  size_t ws_bytes[WS_COUNT] = {};
+  void *host_pinned = nullptr;  // small pinned staging buffer for synchronous scalar results
+  size_t host_pinned_bytes = 0;
+};
+
+namespace openk {
+
+// set the error message and return the status
+inline open_status fail(open_ctx *ctx, open_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+#define OPEN_HIP_TRY(ctx, expr)                                                             \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return ::openk::fail((ctx), OPEN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define OPEN_LAUNCH_CHECK(ctx)                                                              \
+  do {                                                                                      \
+    hipError_t _e = hipGetLastError();                                                      \
+    if (_e != hipSuccess)                                                                   \
+      return ::openk::fail((ctx), OPEN_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+// device workspace of at least `bytes` for slot `slot` (grows, never shrinks)
+open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out);
+open_status pinned_get(open_ctx *ctx, size_t bytes, void **out);
+
+// ---- internal launchers (defined in the .hip files)
+// Row classification + stable counting sort; fills list[m] (row ids grouped by class) and
+// cls[2*kNumClasses] = {start, count} per class, on the device.
+constexpr int kNumClasses = 17;
+constexpr int kSplitClass = 16;  // rows solved by the split-K column path
+open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t **list, int64_t **cls,
+                        int64_t split_min);
+// Ridge solve of all rows given a bucketing.
+open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const int64_t *row_ptr, const int32_t *col,
+                            const float *val, float lambda, int weighted, const int32_t *list, const int64_t *cls,
+                            float *X, int32_t *status, int64_t m);
+open_status splitk_launch(open_ctx *ctx, const float *F, int k, const int64_t *row_ptr, const int32_t *col,
+                          const float *val, float lambda, int weighted, const int32_t *list, const int64_t *cls,
+                          float *X, int32_t *status, int64_t m);
+
+}  // namespace openk

@@ -1,0 +1,10 @@
+// Ridge-solve tier kernels instantiated in their own translation unit (parallel build).
+#include "rowsolve.h"
+
+namespace openk {
+
+open_status tier_k64_d56(OPEN_TIER_ARGS) {
+  return launch_tier<64, 5, 6, true>(OPEN_TIER_PASS, 5, 6, X, status, m);
+}
+
+}  // namespace openk

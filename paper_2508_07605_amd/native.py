@@ -1,0 +1,299 @@
+"""Thin Python binding of libopen (include/open.h).
+
+Argument marshalling only: torch tensors supply device memory and the stream, every step
+of the computation runs in the library's HIP kernels.  The functions carry the C names.
+There is no fallback: if the library is missing or fails to load, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (load torch's HIP runtime before the library binds to it)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libopen.so")
+
+OPEN_OK, OPEN_E_INVALID, OPEN_E_NOMEM, OPEN_E_DEVICE, OPEN_E_UNSUPPORTED = 0, -1, -2, -3, -4
+ROW_OK, ROW_EMPTY, ROW_NONPOS_PIVOT, ROW_NONFINITE, ROW_NONPOS_BASE, ROW_BADINDEX = 0, 1, 2, 3, 4, 5
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_F32 = ctypes.c_float
+_F64 = ctypes.c_double
+
+# name -> (restype, argtypes); mirrors include/open.h
+SIGNATURES = {
+    "open_create": (_I32, [ctypes.POINTER(_P), _I32, _P]),
+    "open_destroy": (_I32, [_P]),
+    "open_set_stream": (_I32, [_P, _P]),
+    "open_last_error": (ctypes.c_char_p, [_P]),
+    "open_sync": (_I32, [_P]),
+    "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
+    "open_csr_to_csc": (_I32, [_P, _I64, _I32, _P, _P, _P, _P, _P, _P]),
+    "open_fit": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
+    "open_objective": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _F32, _I32, _P]),
+    "open_residual": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P]),
+    "open_predict": (_I32, [_P, _P, _I64, _P, _I32, _I32, _P, _P, _P, _I32, _F32, _P, _P, _P]),
+    "open_mlp_create": (_I32, [_P, ctypes.POINTER(_P), _I32, _I32, _I32, _P]),
+    "open_mlp_destroy": (_I32, [_P]),
+    "open_mlp_num_params": (_I64, [_I32, _I32, _I32]),
+    "open_mlp_get_weights": (_I32, [_P, _P]),
+    "open_mlp_set_weights": (_I32, [_P, _P]),
+    "open_mlp_forward": (_I32, [_P, _I64, _P, _P, _P, _P]),
+    "open_mlp_loss_grad": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
+    "open_mlp_train_step": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _I32, _F32, _P]),
+    "open_mlp_foldin": (_I32, [_P, _P, _I64, _P, _P, _P, _F32, _F32, _I32, _P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+class OpenError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libopen status %d: %s" % (status, msg))
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OpenError(OPEN_E_DEVICE, "libopen.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name, numel=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+    return _ptr(t)
+
+
+class Context:
+    """open_ctx bound to a device and to torch's current stream on it."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = L.open_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != OPEN_OK:
+            raise OpenError(st, "open_create failed")
+        self.handle = h
+
+    def check(self, st):
+        if st != OPEN_OK:
+            raise OpenError(st, lib().open_last_error(self.handle).decode())
+
+    def set_stream(self, stream):
+        self._stream = stream
+        self.check(lib().open_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def sync(self):
+        self.check(lib().open_sync(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().open_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def open_foldin(ctx, F, row_ptr, col, val, lam, weighted=True, U_out=None, row_status=None):
+    n, k = F.shape
+    m = row_ptr.numel() - 1
+    if U_out is None:
+        U_out = torch.empty((m, k), dtype=torch.float32, device=F.device)
+    ctx.check(lib().open_foldin(ctx.handle, _dev(F, torch.float32, "F"), n, k, m,
+                                _dev(row_ptr, torch.int64, "row_ptr", m + 1), _dev(col, torch.int32, "col"),
+                                _dev(val, torch.float32, "val"), float(lam), int(bool(weighted)),
+                                _dev(U_out, torch.float32, "U_out", m * k),
+                                _dev(row_status, torch.int32, "row_status", m)))
+    return U_out
+
+
+def open_csr_to_csc(ctx, row_ptr, col, val, n):
+    m = row_ptr.numel() - 1
+    nnz = col.numel()
+    dev = row_ptr.device
+    col_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    row_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    cval = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)
+    ctx.check(lib().open_csr_to_csc(ctx.handle, m, n, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                    _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                    _ptr(col_ptr), _ptr(row_idx), _ptr(cval)))
+    return col_ptr, row_idx[:nnz], cval[:nnz]
+
+
+def open_fit(ctx, row_ptr, col, val, U, V, lam, sweeps, weighted=True, want_obj=False):
+    import numpy as np
+    m, k = U.shape
+    n = V.shape[0]
+    obj = np.zeros(2 * sweeps) if want_obj else None
+    ctx.check(lib().open_fit(ctx.handle, m, n, k, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                             _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"), float(lam),
+                             int(bool(weighted)), int(sweeps), _dev(U, torch.float32, "U", m * k),
+                             _dev(V, torch.float32, "V", n * k),
+                             obj.ctypes.data_as(ctypes.c_void_p) if obj is not None else None))
+    return obj
+
+
+def open_objective(ctx, row_ptr, col, val, U, V, lam, weighted=True):
+    m, k = U.shape
+    n = V.shape[0]
+    out = ctypes.c_double()
+    ctx.check(lib().open_objective(ctx.handle, m, n, k, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                   _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                   _dev(U, torch.float32, "U", m * k), _dev(V, torch.float32, "V", n * k),
+                                   float(lam), int(bool(weighted)), ctypes.byref(out)))
+    return out.value
+
+
+def open_residual(ctx, row_ptr, col, val, U, V, rho=None):
+    m, k = U.shape
+    n = V.shape[0]
+    if rho is None:
+        rho = torch.empty(m, dtype=torch.float32, device=U.device)
+    ctx.check(lib().open_residual(ctx.handle, m, n, k, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                  _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                  _dev(U, torch.float32, "U", m * k), _dev(V, torch.float32, "V", n * k),
+                                  _dev(rho, torch.float32, "rho", m)))
+    return rho
+
+
+def open_predict(ctx, U, V, cap_cpu, cap_gpu, base, gamma, P=None, best_idx=None, best_saving=None,
+                 row_status=None):
+    m, k = U.shape
+    n = V.shape[0]
+    dev = U.device
+    if best_idx is None:
+        best_idx = torch.empty(m, dtype=torch.int32, device=dev)
+    if best_saving is None:
+        best_saving = torch.empty(m, dtype=torch.float32, device=dev)
+    ctx.check(lib().open_predict(ctx.handle, _dev(U, torch.float32, "U", m * k), m, _dev(V, torch.float32, "V", n * k),
+                                 n, k, _dev(P, torch.float32, "P", m * n), _dev(cap_cpu, torch.float32, "cap_cpu", n),
+                                 _dev(cap_gpu, torch.float32, "cap_gpu", n), int(base), float(gamma),
+                                 _dev(best_idx, torch.int32, "best_idx", m),
+                                 _dev(best_saving, torch.float32, "best_saving", m),
+                                 _dev(row_status, torch.int32, "row_status", m)))
+    return best_idx, best_saving
+
+
+def open_mlp_num_params(n, k, hidden=256):
+    return int(lib().open_mlp_num_params(n, k, hidden))
+
+
+class Surrogate:
+    """open_mlp handle: the fold-in surrogate network."""
+
+    def __init__(self, ctx, n, k, hidden=256, init=None):
+        import numpy as np
+        self.ctx, self.n, self.k, self.hidden = ctx, n, k, hidden
+        self.num_params = open_mlp_num_params(n, k, hidden)
+        buf = None
+        if init is not None:
+            buf = np.ascontiguousarray(init, dtype=np.float32)
+            if buf.size != self.num_params:
+                raise ValueError("init holds %d values, needs %d" % (buf.size, self.num_params))
+        h = ctypes.c_void_p()
+        ctx.check(lib().open_mlp_create(ctx.handle, ctypes.byref(h), n, k, hidden,
+                                        buf.ctypes.data_as(ctypes.c_void_p) if buf is not None else None))
+        self.handle = h
+
+    def get_weights(self):
+        import numpy as np
+        out = np.empty(self.num_params, dtype=np.float32)
+        self.ctx.check(lib().open_mlp_get_weights(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_weights(self, w):
+        import numpy as np
+        buf = np.ascontiguousarray(w, dtype=np.float32)
+        if buf.size != self.num_params:
+            raise ValueError("weights hold %d values, needs %d" % (buf.size, self.num_params))
+        self.ctx.check(lib().open_mlp_set_weights(self.handle, buf.ctypes.data_as(ctypes.c_void_p)))
+
+    def forward(self, row_ptr, col, val, out=None):
+        m = row_ptr.numel() - 1
+        if out is None:
+            out = torch.empty((m, self.k), dtype=torch.float32, device=row_ptr.device)
+        self.ctx.check(lib().open_mlp_forward(self.handle, m, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                              _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                              _dev(out, torch.float32, "out", m * self.k)))
+        return out
+
+    def loss_grad(self, row_ptr, col, val, target):
+        import numpy as np
+        m = row_ptr.numel() - 1
+        grads = np.empty(self.num_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        self.ctx.check(lib().open_mlp_loss_grad(self.handle, m, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                                _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                                _dev(target, torch.float32, "target", m * self.k),
+                                                ctypes.byref(loss), grads.ctypes.data_as(ctypes.c_void_p)))
+        return loss.value, grads
+
+    def train_step(self, row_ptr, col, val, target, rows, lr, loss_out=None):
+        m = row_ptr.numel() - 1
+        batch = rows.numel() if rows is not None else m
+        self.ctx.check(lib().open_mlp_train_step(self.handle, m, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                                 _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                                 _dev(target, torch.float32, "target", m * self.k),
+                                                 _dev(rows, torch.int64, "rows"), int(batch), float(lr),
+                                                 _dev(loss_out, torch.float32, "loss_out", 1)))
+
+    def foldin(self, F, row_ptr, col, val, tau, lam, weighted=True, U_out=None, used_fallback=None, rho=None,
+               count=True):
+        m = row_ptr.numel() - 1
+        if U_out is None:
+            U_out = torch.empty((m, self.k), dtype=torch.float32, device=F.device)
+        nf = ctypes.c_int64(-1)
+        self.ctx.check(lib().open_mlp_foldin(self.handle, _dev(F, torch.float32, "F"), m,
+                                             _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                             _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                             float(tau), float(lam), int(bool(weighted)),
+                                             _dev(U_out, torch.float32, "U_out", m * self.k),
+                                             _dev(used_fallback, torch.uint8, "used_fallback", m),
+                                             _dev(rho, torch.float32, "rho", m),
+                                             ctypes.byref(nf) if count else None))
+        return U_out, (nf.value if count else None)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().open_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

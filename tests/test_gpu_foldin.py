@@ -1,0 +1,125 @@
+"""GPU parity of the batched ridge solve (fold-in; ALS row/column half-sweeps) against the
+FP64 oracle, through the C ABI.  Per-row relative error e_i = |u_gpu - u_ref| / |u_ref| must
+not exceed 1e-4 (float32 arithmetic, float64 reference); statuses must match exactly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2508_07605_amd import native, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def csr_from_counts(r, counts, n):
+    rp = np.zeros(len(counts) + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(counts)
+    col = np.concatenate([np.sort(r.choice(n, size=c, replace=False)) for c in counts] or [np.zeros(0)])
+    val = r.uniform(0.4, 1.0, size=int(rp[-1])).astype(np.float32)
+    return rp, col.astype(np.int32), val
+
+
+def run_gpu(ctx, F, rp, col, val, lam, weighted=True):
+    st = torch.full((len(rp) - 1,), -7, dtype=torch.int32, device="cuda")
+    U = native.open_foldin(ctx, dev(F), dev(rp), dev(col), dev(val), lam, weighted, row_status=st)
+    torch.cuda.synchronize()
+    return U.cpu().numpy().astype(np.float64), st.cpu().numpy()
+
+
+def rel_err(U, ref):
+    nrm = np.linalg.norm(ref, axis=1)
+    return np.linalg.norm(U - ref, axis=1) / np.where(nrm > 0, nrm, 1.0)
+
+
+def report(name, e):
+    print("%s: rows %d  max %.3e  p99 %.3e  median %.3e" % (name, len(e), e.max(), np.percentile(e, 99),
+                                                            np.median(e)))
+
+
+def test_foldin_config_shape(ctx):
+    # the batched fold-in workload at reduced row count: k = 32, 480 settings, 4..24 observed,
+    # ragged tail (m not a multiple of 16 or of the 1024-row bucketing tile)
+    grid = synth.grid_of("foldin")
+    V = synth.setting_factors(3, grid, 32, m_ref=2048)
+    rows = synth.draw_rows(3, grid, 20_003, ("uniform", 4, 24), seed=11)
+    U, st = run_gpu(ctx, V, rows.row_ptr, rows.col, rows.val, 0.05)
+    ref, ref_st = oracle.ridge_rows(rows.row_ptr, rows.col, rows.val, V, 0.05, True)
+    assert np.array_equal(st, ref_st)
+    e = rel_err(U, ref)
+    report("foldin k32", e)
+    assert e.max() <= TOL
+
+
+@pytest.mark.parametrize("k,n,maxc", [(8, 120, 120), (16, 120, 120), (32, 480, 480), (64, 480, 32)])
+@pytest.mark.parametrize("weighted", [True, False])
+def test_every_size_class(ctx, k, n, maxc, weighted):
+    # every count from 0 to maxc at least a few times: empty rows, all dual classes and,
+    # for k <= 32, the primal classes
+    r = np.random.default_rng(100 + k)
+    counts = np.concatenate([np.repeat(np.arange(0, maxc + 1), 3), r.integers(0, maxc + 1, size=517)])
+    r.shuffle(counts)
+    rp, col, val = csr_from_counts(r, counts, n)
+    V = (r.normal(size=(n, k)) * 0.3).astype(np.float32)
+    U, st = run_gpu(ctx, V, rp, col, val, 0.05, weighted)
+    ref, ref_st = oracle.ridge_rows(rp, col, val, V, 0.05, weighted)
+    assert np.array_equal(st, ref_st)
+    assert (U[counts == 0] == 0).all()
+    e = rel_err(U, ref)[counts > 0]
+    report("classes k%d n%d w%d" % (k, n, weighted), e)
+    assert e.max() <= TOL
+
+
+def test_status_codes(ctx):
+    r = np.random.default_rng(5)
+    k, n = 32, 64
+    V = (r.normal(size=(n, k)) * 0.3).astype(np.float32)
+    V[7] = 0.0
+    counts = [0, 5, 5, 40, 5]
+    rp, col, val = csr_from_counts(r, counts, n)
+    val[rp[2]] = np.nan         # row 2: non-finite value (dual)
+    val[rp[3] + 3] = np.inf     # row 3: non-finite value (primal)
+    col[rp[4]:rp[5]] = np.array([1, 7, 20, 30, 40], dtype=np.int32)  # row 4 observes the zero factor row
+    U, st = run_gpu(ctx, V, rp, col, val, 0.05)
+    assert st.tolist() == [1, 0, 3, 3, 0]
+    assert (U[[0, 2, 3]] == 0).all()
+    # lambda = 0 with an observed all-zero factor row: the dual system has an exact zero pivot
+    U0, st0 = run_gpu(ctx, V, rp, col, val, 0.0)
+    assert st0[4] == 2 and (U0[4] == 0).all()
+
+
+def test_deterministic(ctx):
+    grid = synth.grid_of("foldin")
+    V = synth.setting_factors(3, grid, 32, m_ref=1024)
+    rows = synth.draw_rows(3, grid, 7001, ("uniform", 1, 60), seed=12)
+    a, _ = run_gpu(ctx, V, rows.row_ptr, rows.col, rows.val, 0.05)
+    b, _ = run_gpu(ctx, V, rows.row_ptr, rows.col, rows.val, 0.05)
+    assert np.array_equal(a, b)
+
+
+def test_full_size_sampled(ctx):
+    # the full batched fold-in (1M new rows) in the launch configuration the benchmark times;
+    # the oracle recomputes a seeded sample of rows
+    c = synth.CONFIGS["foldin"]
+    grid = synth.grid_of("foldin")
+    V = synth.setting_factors(c["cfg_id"], grid, c["k"])
+    rows = synth.draw_rows(c["cfg_id"], grid, c["m"], c["counts"], seed=0)
+    U, st = run_gpu(ctx, V, rows.row_ptr, rows.col, rows.val, c["lam"])
+    assert (st == 0).all()
+    sample = np.sort(np.random.default_rng(9).choice(rows.m, size=20_000, replace=False))
+    ref, ref_st = oracle.ridge_subset(sample, rows.row_ptr, rows.col, rows.val, V, c["lam"], True)
+    e = rel_err(U[sample], ref)
+    report("foldin full-size sample", e)
+    assert e.max() <= TOL
+    assert np.isfinite(U).all()
