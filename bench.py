@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the CF-completion hot path on one MI355X.
+
+Workload (one step): batched fold-in of 1,000,000 new applications, each with 4..24
+observed settings out of 480 (24 CPU caps x 20 GPU caps), against fixed 480 x 32 float32
+setting factors (rank 32, weighted lambda = 0.05), through libopen's C ABI.  Inputs are
+synthetic and already resident in HBM when the timed region starts.
+
+Printed: one JSON line with the throughput in rows/s, the roofline of the dominant kernel
+(live HIP-event timing of every kernel the library launches), the FP64 CPU oracle timed on
+a bounded sample of the same rows, and the prediction RMSE of both against the noiseless
+truth on unobserved entries.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (vector and matrix)
+PEAK_HBM_GBS = 8000.0
+
+
+def dual_flops(n, k):
+    # Gram n(n+1)k (symmetric), LDL^T/Cholesky n^3/3, two triangular solves 2n^2, output 2nk
+    return n * (n + 1) * k + n ** 3 / 3.0 + 2 * n * n + 2 * n * k
+
+
+def primal_flops(n, k):
+    return n * k * (k + 1) + 2 * n * k + k ** 3 / 3.0 + 2 * k * k
+
+
+def row_flops(n, k):
+    import numpy as np
+    n = np.asarray(n, dtype=np.float64)
+    dual = n <= min(k, 32)
+    return np.where(n == 0, 0.0, np.where(dual, dual_flops(n, k), primal_flops(n, k)))
+
+
+def tier_of_counts(n, k):
+    """Name of the ridge kernel that solves a row with n observations (matches the library)."""
+    import numpy as np
+    n = np.asarray(n)
+    out = np.empty(n.shape, dtype=object)
+    dmax = min(k, 32)
+    out[n <= 16] = "d14"
+    out[(n > 16) & (n <= 24)] = "d56"
+    out[(n > 24) & (n <= dmax)] = "d78"
+    out[n > dmax] = "primal"
+    if k == 8:
+        out[n <= 8] = "dual"
+    if k == 16:
+        out[n <= 16] = "dual"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--rows", type=int, default=None, help="override the 1,000,000 new rows")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle work for the CPU baseline")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 256 MiB device copy (reference kernel for HBM counter scaling)")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; the data-parallel path shards rows across GPUs "
+              "with no exchange (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    cfg = synth.CONFIGS["foldin"]
+    k, lam = cfg["k"], cfg["lam"]
+    m = args.rows or cfg["m"]
+    grid = synth.grid_of("foldin")
+    t0 = time.time()
+    V = synth.setting_factors(cfg["cfg_id"], grid, k)
+    rows = synth.draw_rows(cfg["cfg_id"], grid, m, cfg["counts"], seed=0)
+    print("bench: generated %d rows (%d nnz) in %.1f s" % (m, rows.nnz, time.time() - t0), file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    dV, drp, dcol, dval = to(V), to(rows.row_ptr), to(rows.col), to(rows.val)
+    dU = torch.empty((m, k), dtype=torch.float32, device=dev)
+    dst = torch.empty(m, dtype=torch.int32, device=dev)
+    ctx = native.Context(0)
+
+    def step():
+        native.open_foldin(ctx, dV, drp, dcol, dval, lam, True, U_out=dU, row_status=dst)
+
+    if args.copy_calib:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = m / (ms * 1e-3)
+    print("bench: %d steps, %.3f ms/step, %.3e rows/s" % (args.steps, ms, value), file=sys.stderr, flush=True)
+    st = dst.cpu().numpy()
+    assert (st == 0).all(), "row status not ok: %s" % np.bincount(st)
+
+    # live per-kernel timing (HIP events around each launch, on the library's stream)
+    ctx.profile(True)
+    for _ in range(args.profile_steps):
+        step()
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    counts = rows.counts()
+    tiers = tier_of_counts(counts, k)
+    flops = row_flops(counts, k)
+    kernels = {}
+    for name, (tot, launches) in prof.items():
+        avg_ms = tot / launches
+        kernels[name] = avg_ms
+    ridge = {n: t for n, t in kernels.items() if n.startswith("ridge_")}
+    dom = max(ridge, key=ridge.get)
+    tier = dom.split("_")[-1]
+    sel = tiers == tier
+    dom_flops = float(flops[sel].sum())
+    dom_rows = int(sel.sum())
+    dom_bytes = float((8 * counts[sel] + 8 + 4 * k).sum())
+    dom_ms = ridge[dom]
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "kernel": dom, "kernel_ms": round(dom_ms, 4), "kernel_rows": dom_rows,
+        "algorithmic_flops": dom_flops, "algorithmic_bytes": dom_bytes,
+        "hbm_gbs": round(dom_bytes / (dom_ms * 1e-3) / 1e9, 1),
+    }
+    all_flops = float(flops.sum())
+    pass_tflops = all_flops / (ms * 1e-3) / 1e12
+    print("bench: kernels %s" % json.dumps({n: round(t, 4) for n, t in kernels.items()}), file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "fold-in rows/sec at rank 32 (ALS vs MLP) at equal RMSE vs FP64 oracle",
+        "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched ALS fold-in: %d new apps x 480 settings (24 CPU x 20 GPU caps), "
+                               "4-24 observed per app, rank 32, weighted lambda 0.05, fixed float32 setting factors"
+                               % m, "rows": m, "settings": grid.n, "rank": k, "nnz": rows.nnz,
+                   "parallelism": "single GPU"},
+        "pass_tflops": round(pass_tflops, 3),
+        "roofline": roofline,
+    }
+
+    # accuracy: both fold-ins against the noiseless truth on unobserved settings of sampled rows
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.max_threads()
+        rs = np.random.default_rng(2025)
+        probe = np.sort(rs.choice(m, size=min(m, 20_000), replace=False))
+        t1 = time.perf_counter()
+        oracle.ridge_subset(probe, rows.row_ptr, rows.col, rows.val, V, lam, True)
+        per_row = (time.perf_counter() - t1) / len(probe)
+        ns = int(min(m, max(len(probe), args.cpu_seconds / max(per_row, 1e-9))))
+        sample = np.sort(rs.choice(m, size=ns, replace=False))
+        t1 = time.perf_counter()
+        Uref, st_ref = oracle.ridge_subset(sample, rows.row_ptr, rows.col, rows.val, V, lam, True)
+        cpu_s = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": ns / cpu_s, "unit": "rows/s", "cores": threads, "kind": "oracle",
+                               "sample": "%d of the %d rows (seeded), FP64 primal ridge solves, %.1f s" % (ns, m, cpu_s)}
+        ev = sample[:20_000]
+        Ug = dU[torch.from_numpy(ev).to(dev)].cpu().numpy().astype(np.float64)
+        Uo = Uref[:len(ev)]
+        T = synth.truth_dense(rows.apps.take(ev), grid)
+        obs = np.zeros_like(T, dtype=bool)
+        sub_rp = rows.row_ptr
+        for j, i in enumerate(ev):
+            obs[j, rows.col[sub_rp[i]:sub_rp[i + 1]]] = True
+        Vd = V.astype(np.float64)
+        rmse_g = float(np.sqrt((((Ug @ Vd.T) - T)[~obs] ** 2).mean()))
+        rmse_o = float(np.sqrt((((Uo @ Vd.T) - T)[~obs] ** 2).mean()))
+        e = np.linalg.norm(Ug - Uo, axis=1) / np.linalg.norm(Uo, axis=1)
+        out["accuracy"] = {"rows": len(ev), "rmse_gpu": rmse_g, "rmse_oracle": rmse_o,
+                           "rmse_gap": abs(rmse_g - rmse_o), "max_rel_err_vs_oracle": float(e.max()),
+                           "accuracy_pct_1_minus_mape": float(100 * (1 - np.abs(((Ug @ Vd.T) - T)[~obs] /
+                                                                               T[~obs]).mean()))}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

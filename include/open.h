@@ -68,6 +68,15 @@ const char *open_last_error(const open_ctx *ctx);
 /* Block until the context's stream has drained. */
 open_status open_sync(open_ctx *ctx);
 
+/* Per-kernel timing: when enabled, every kernel the context launches is bracketed by HIP
+ * events on its stream.  open_profile_read drains the stream and reports, per kernel name
+ * (static strings owned by the library), the summed duration in milliseconds and the launch
+ * count; it returns the number of distinct kernels (entries beyond `max` are dropped) or -1
+ * on error, and forgets the records when reset != 0. */
+open_status open_profile(open_ctx *ctx, int32_t enable);
+int32_t open_profile_read(open_ctx *ctx, const char **names, double *total_ms, int64_t *launches, int32_t max,
+                          int32_t reset);
+
 /*
  * Fold-in (Section III-B.2: a new application's few profiled entries become a sparse row
  * whose missing entries collaborative filtering fills).  With the setting factors F (n x k)

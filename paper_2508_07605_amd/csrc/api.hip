@@ -49,6 +49,29 @@ open_status pinned_get(open_ctx *ctx, size_t bytes, void **out) {
   return OPEN_OK;
 }
 
+static hipEvent_t prof_event(open_ctx *ctx) {
+  if (ctx->prof_pool_used == ctx->prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->prof_pool.push_back(e);
+  }
+  return ctx->prof_pool[ctx->prof_pool_used++];
+}
+
+void prof_begin(open_ctx *ctx, const char *name) {
+  if (!ctx->prof_on) return;
+  open_ctx::ProfRec r{name, prof_event(ctx), prof_event(ctx)};
+  if (r.beg && r.end) {
+    (void)hipEventRecord(r.beg, ctx->stream);
+    ctx->prof_recs.push_back(r);
+  }
+}
+
+void prof_end(open_ctx *ctx) {
+  if (!ctx->prof_on || ctx->prof_recs.empty()) return;
+  (void)hipEventRecord(ctx->prof_recs.back().end, ctx->stream);
+}
+
 static bool rank_ok(int k) { return k == 8 || k == 16 || k == 32 || k == 64; }
 
 // Validate a CSR header shared by several calls.
@@ -95,6 +118,7 @@ open_status open_destroy(open_ctx *ctx) {
   for (int i = 0; i < open_ctx::WS_COUNT; ++i)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   delete ctx;
   return OPEN_OK;
 }
@@ -108,6 +132,45 @@ open_status open_set_stream(open_ctx *ctx, void *hip_stream) {
 const char *open_last_error(const open_ctx *ctx) {
   if (!ctx) return "null context";
   return ctx->err.c_str();
+}
+
+open_status open_profile(open_ctx *ctx, int32_t enable) {
+  if (!ctx) return OPEN_E_INVALID;
+  ctx->prof_on = enable != 0;
+  return OPEN_OK;
+}
+
+int32_t open_profile_read(open_ctx *ctx, const char **names, double *total_ms, int64_t *launches, int32_t max,
+                          int32_t reset) {
+  if (!ctx) return -1;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return -1;
+  std::vector<const char *> nm;
+  std::vector<double> tot;
+  std::vector<int64_t> cnt;
+  for (const auto &r : ctx->prof_recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.beg, r.end) != hipSuccess) continue;
+    size_t i = 0;
+    while (i < nm.size() && strcmp(nm[i], r.name) != 0) ++i;
+    if (i == nm.size()) {
+      nm.push_back(r.name);
+      tot.push_back(0.0);
+      cnt.push_back(0);
+    }
+    tot[i] += ms;
+    cnt[i] += 1;
+  }
+  const int32_t n = (int32_t)nm.size();
+  for (int32_t i = 0; i < n && i < max; ++i) {
+    if (names) names[i] = nm[i];
+    if (total_ms) total_ms[i] = tot[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  if (reset) {
+    ctx->prof_recs.clear();
+    ctx->prof_pool_used = 0;
+  }
+  return n;
 }
 
 open_status open_sync(open_ctx *ctx) {

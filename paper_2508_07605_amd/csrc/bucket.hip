@@ -29,7 +29,15 @@ __device__ __forceinline__ int row_class(int64_t cnt, int k, int64_t split_min) 
   return 9 + p;
 }
 
-__global__ __launch_bounds__(kBucketThreads) void k_class_count(int64_t m, const int64_t *__restrict__ ptr, int k,
+// mask (nullable): rows with mask[i] == 0 are left out of every class
+__device__ __forceinline__ int row_class_m(const int64_t *__restrict__ ptr, const uint8_t *__restrict__ mask, int64_t i,
+                                           int k, int64_t split_min) {
+  if (mask && !mask[i]) return -1;
+  return row_class(ptr[i + 1] - ptr[i], k, split_min);
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_class_count(int64_t m, const int64_t *__restrict__ ptr,
+                                                                const uint8_t *__restrict__ mask, int k,
                                                                 int64_t split_min, int32_t *__restrict__ hist) {
   __shared__ int h[kNumClasses];
   if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
@@ -37,14 +45,17 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_count(int64_t m, const
   const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock;
   for (int r = threadIdx.x; r < kRowsPerBlock; r += kBucketThreads) {
     const int64_t i = base + r;
-    if (i < m) atomicAdd(&h[row_class(ptr[i + 1] - ptr[i], k, split_min)], 1);
+    if (i < m) {
+      const int c = row_class_m(ptr, mask, i, k, split_min);
+      if (c >= 0) atomicAdd(&h[c], 1);
+    }
   }
   __syncthreads();
   if (threadIdx.x < kNumClasses) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
 // Exclusive scan of the class-major histogram (one block); cls[2c] = start, cls[2c+1] = count.
-__global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist, int nblk, int64_t m,
+__global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist, int nblk,
                                                      int64_t *__restrict__ cls) {
   __shared__ int64_t part[1024];
   const int total = kNumClasses * nblk;
@@ -61,6 +72,7 @@ __global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist,
     part[threadIdx.x] += v;
     __syncthreads();
   }
+  const int64_t total_rows = part[1023];
   int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
   for (int i = b0; i < b1; ++i) {
     const int64_t h = hist[i];
@@ -70,14 +82,15 @@ __global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist,
   __syncthreads();
   if (threadIdx.x < kNumClasses) {
     const int c = threadIdx.x;
-    const int64_t start = hist[(int64_t)c * nblk];
-    const int64_t end = c + 1 < kNumClasses ? (int64_t)hist[(int64_t)(c + 1) * nblk] : m;
+    const int64_t start = nblk > 0 ? (int64_t)hist[(int64_t)c * nblk] : 0;
+    const int64_t end = c + 1 < kNumClasses && nblk > 0 ? (int64_t)hist[(int64_t)(c + 1) * nblk] : total_rows;
     cls[2 * c] = start;
     cls[2 * c + 1] = end - start;
   }
 }
 
-__global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const int64_t *__restrict__ ptr, int k,
+__global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const int64_t *__restrict__ ptr,
+                                                                const uint8_t *__restrict__ mask, int k,
                                                                 int64_t split_min, const int32_t *__restrict__ offs,
                                                                 int32_t *__restrict__ list) {
   __shared__ int wcnt[kBucketThreads / kWave][kNumClasses];
@@ -87,7 +100,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
   __syncthreads();
   for (int pass = 0; pass < kRowsPerBlock / kBucketThreads; ++pass) {
     const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + pass * kBucketThreads + tid;
-    const int c = i < m ? row_class(ptr[i + 1] - ptr[i], k, split_min) : -1;
+    const int c = i < m ? row_class_m(ptr, mask, i, k, split_min) : -1;
     int rank = 0;
     for (int cc = 0; cc < kNumClasses; ++cc) {
       const unsigned long long mask = __ballot(c == cc);
@@ -111,7 +124,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
 }
 
 open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t **list, int64_t **cls,
-                        int64_t split_min) {
+                        int64_t split_min, const uint8_t *mask) {
   const int nblk = (int)((m + kRowsPerBlock - 1) / kRowsPerBlock);
   void *hist = nullptr, *lst = nullptr, *c = nullptr;
   open_status st;
@@ -120,16 +133,13 @@ open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k,
   if ((st = ws_get(ctx, open_ctx::WS_LIST, sizeof(int32_t) * (size_t)(m > 0 ? m : 1), &lst))) return st;
   if ((st = ws_get(ctx, open_ctx::WS_CLS, sizeof(int64_t) * 2 * kNumClasses, &c))) return st;
   if (m > 0) {
-    hipLaunchKernelGGL(k_class_count, dim3(nblk), dim3(kBucketThreads), 0, ctx->stream, m, row_ptr, k, split_min,
-                       (int32_t *)hist);
-    OPEN_LAUNCH_CHECK(ctx);
+    OPEN_LAUNCH(ctx, "bucket_count", k_class_count, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask, k,
+                split_min, (int32_t *)hist);
   }
-  hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, ctx->stream, (int32_t *)hist, nblk, m, (int64_t *)c);
-  OPEN_LAUNCH_CHECK(ctx);
+  OPEN_LAUNCH(ctx, "bucket_scan", k_class_scan, dim3(1), dim3(1024), 0, (int32_t *)hist, nblk, (int64_t *)c);
   if (m > 0) {
-    hipLaunchKernelGGL(k_class_place, dim3(nblk), dim3(kBucketThreads), 0, ctx->stream, m, row_ptr, k, split_min,
-                       (const int32_t *)hist, (int32_t *)lst);
-    OPEN_LAUNCH_CHECK(ctx);
+    OPEN_LAUNCH(ctx, "bucket_place", k_class_place, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask, k,
+                split_min, (const int32_t *)hist, (int32_t *)lst);
   }
   *list = (int32_t *)lst;
   *cls = (int64_t *)c;

@@ -7,6 +7,7 @@
 
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "../../include/open.h"
 
@@ -97,6 +98,15 @@ struct open_ctx {
   size_t ws_bytes[WS_COUNT] = {};
   void *host_pinned = nullptr;  // small pinned staging buffer for synchronous scalar results
   size_t host_pinned_bytes = 0;
+  // optional per-kernel timing (HIP events around each launch)
+  bool prof_on = false;
+  struct ProfRec {
+    const char *name;
+    hipEvent_t beg, end;
+  };
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_pool_used = 0;
 };
 
 namespace openk {
@@ -121,6 +131,17 @@ inline open_status fail(open_ctx *ctx, open_status st, const std::string &msg) {
       return ::openk::fail((ctx), OPEN_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(_e)); \
   } while (0)
 
+// Kernel launch on the context's stream, timed with events when profiling is on.
+void prof_begin(open_ctx *ctx, const char *name);
+void prof_end(open_ctx *ctx);
+#define OPEN_LAUNCH(ctx, name, kernel, grid, block, shmem, ...)                          \
+  do {                                                                                   \
+    ::openk::prof_begin((ctx), (name));                                                  \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, (ctx)->stream, __VA_ARGS__);          \
+    ::openk::prof_end(ctx);                                                              \
+    OPEN_LAUNCH_CHECK(ctx);                                                              \
+  } while (0)
+
 // device workspace of at least `bytes` for slot `slot` (grows, never shrinks)
 open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out);
 open_status pinned_get(open_ctx *ctx, size_t bytes, void **out);
@@ -131,7 +152,10 @@ open_status pinned_get(open_ctx *ctx, size_t bytes, void **out);
 constexpr int kNumClasses = 17;
 constexpr int kSplitClass = 16;  // rows solved by the split-K column path
 open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t **list, int64_t **cls,
-                        int64_t split_min);
+                        int64_t split_min, const uint8_t *mask = nullptr);
+// Column view on the device (stable counting sort); entries with a column outside [0, n) are dropped.
+open_status csr_to_csc_dev(open_ctx *ctx, int64_t m, int n, const int64_t *row_ptr, const int32_t *col,
+                           const float *val, int64_t *col_ptr, int32_t *row_idx, float *cval);
 // Ridge solve of all rows given a bucketing.
 open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const int64_t *row_ptr, const int32_t *col,
                             const float *val, float lambda, int weighted, const int32_t *list, const int64_t *cls,

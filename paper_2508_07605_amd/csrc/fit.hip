@@ -137,19 +137,17 @@ static open_status check_cols(open_ctx *ctx, int64_t nnz, const int32_t *col, in
   open_status st;
   if ((st = ws_get(ctx, open_ctx::WS_FLAG, 256, &flag))) return st;
   if ((st = pinned_get(ctx, 64, (void **)&h))) return st;
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, ctx->stream, (int *)flag, 1, 0);
-  OPEN_LAUNCH_CHECK(ctx);
+  OPEN_LAUNCH(ctx, "fill", k_fill_i32, dim3(1), dim3(64), 0, (int *)flag, 1, 0);
   int64_t blocks = (nnz + 255) / 256;
   if (blocks > ctx->num_cu * 8) blocks = ctx->num_cu * 8;
-  hipLaunchKernelGGL(k_check_cols, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, nnz, col, n, (int *)flag);
-  OPEN_LAUNCH_CHECK(ctx);
+  OPEN_LAUNCH(ctx, "check_cols", k_check_cols, dim3((unsigned)blocks), dim3(256), 0, nnz, col, n, (int *)flag);
   OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (h[0]) return fail(ctx, OPEN_E_INVALID, "a column index lies outside [0, n)");
   return OPEN_OK;
 }
 
-static open_status csr_to_csc_impl(open_ctx *ctx, int64_t m, int n, const int64_t *row_ptr, const int32_t *col,
+open_status csr_to_csc_dev(open_ctx *ctx, int64_t m, int n, const int64_t *row_ptr, const int32_t *col,
                                    const float *val, int64_t *col_ptr, int32_t *row_idx, float *cval) {
   const int nchunk = (int)((m + kChunkRows - 1) / kChunkRows);
   const int64_t len = (int64_t)n * nchunk;
@@ -161,25 +159,19 @@ static open_status csr_to_csc_impl(open_ctx *ctx, int64_t m, int n, const int64_
   if ((st = ws_get(ctx, open_ctx::WS_RED, sizeof(int64_t) * (size_t)(nb > 0 ? nb : 1), &bsum))) return st;
   const int blocks = (nchunk + kCscWaves - 1) / kCscWaves;
   if (nchunk > 0) {
-    hipLaunchKernelGGL(k_csc_count, dim3(blocks), dim3(kCscWaves * 64), sizeof(int) * kCscWaves * n, ctx->stream, m,
-                       n, row_ptr, col, nchunk, (int32_t *)hist);
-    OPEN_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(1024), 0, ctx->stream, (const int32_t *)hist, len,
-                       (int64_t *)base, (int64_t *)bsum);
-    OPEN_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, ctx->stream, (int64_t *)bsum, nb);
-    OPEN_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(1024), 0, ctx->stream, (int64_t *)base, len,
-                       (const int64_t *)bsum);
-    OPEN_LAUNCH_CHECK(ctx);
+    OPEN_LAUNCH(ctx, "csc_count", k_csc_count, dim3(blocks), dim3(kCscWaves * 64), sizeof(int) * kCscWaves * n, m, n,
+                row_ptr, col, nchunk, (int32_t *)hist);
+    OPEN_LAUNCH(ctx, "scan_blocks", k_scan_blocks, dim3((unsigned)nb), dim3(1024), 0, (const int32_t *)hist, len,
+                (int64_t *)base, (int64_t *)bsum);
+    OPEN_LAUNCH(ctx, "scan_sums", k_scan_sums, dim3(1), dim3(1024), 0, (int64_t *)bsum, nb);
+    OPEN_LAUNCH(ctx, "scan_add", k_scan_add, dim3((unsigned)nb), dim3(1024), 0, (int64_t *)base, len,
+                (const int64_t *)bsum);
   }
-  hipLaunchKernelGGL(k_colptr, dim3((n + 1 + 255) / 256), dim3(256), 0, ctx->stream, (const int64_t *)base,
-                     (const int32_t *)hist, n, nchunk, col_ptr);
-  OPEN_LAUNCH_CHECK(ctx);
+  OPEN_LAUNCH(ctx, "csc_colptr", k_colptr, dim3((n + 1 + 255) / 256), dim3(256), 0, (const int64_t *)base,
+              (const int32_t *)hist, n, nchunk, col_ptr);
   if (nchunk > 0) {
-    hipLaunchKernelGGL(k_csc_place, dim3(blocks), dim3(kCscWaves * 64), sizeof(int64_t) * kCscWaves * n, ctx->stream,
-                       m, n, row_ptr, col, val, nchunk, (const int64_t *)base, row_idx, cval);
-    OPEN_LAUNCH_CHECK(ctx);
+    OPEN_LAUNCH(ctx, "csc_place", k_csc_place, dim3(blocks), dim3(kCscWaves * 64), sizeof(int64_t) * kCscWaves * n, m,
+                n, row_ptr, col, val, nchunk, (const int64_t *)base, row_idx, cval);
   }
   return OPEN_OK;
 }
@@ -191,7 +183,7 @@ constexpr int kRedBlocks = 1024;
 // in float32 and added to a per-lane float64 accumulator; lanes and waves are combined in
 // a fixed order, then a second kernel adds the block partials in order.
 template <int K>
-__global__ __launch_bounds__(256) void k_objective_rows(int64_t m, const int64_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void k_objective_rows(int64_t m, int n, const int64_t *__restrict__ ptr,
                                                         const int32_t *__restrict__ col,
                                                         const float *__restrict__ val, const float *__restrict__ U,
                                                         const float *__restrict__ V, float lambda, int weighted,
@@ -204,7 +196,9 @@ __global__ __launch_bounds__(256) void k_objective_rows(int64_t m, const int64_t
     const float *u = U + i * K;
     const int64_t b = ptr[i], e = ptr[i + 1];
     for (int64_t t = b + lane; t < e; t += 64) {
-      const float *v = V + (int64_t)col[t] * K;
+      const int j = col[t];
+      if (j < 0 || j >= n) continue;
+      const float *v = V + (int64_t)j * K;
       float p = 0.f;
 #pragma unroll
       for (int a = 0; a < K; ++a) p = __builtin_fmaf(u[a], v[a], p);
@@ -251,7 +245,7 @@ __global__ __launch_bounds__(256) void k_objective_cols(int n, const int64_t *__
 }
 
 template <int K>
-__global__ __launch_bounds__(256) void k_residual(int64_t m, const int64_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void k_residual(int64_t m, int n, const int64_t *__restrict__ ptr,
                                                   const int32_t *__restrict__ col, const float *__restrict__ val,
                                                   const float *__restrict__ U, const float *__restrict__ V,
                                                   float *__restrict__ rho) {
@@ -262,7 +256,9 @@ __global__ __launch_bounds__(256) void k_residual(int64_t m, const int64_t *__re
     const int64_t b = ptr[i], e = ptr[i + 1];
     float acc = 0.f;
     for (int64_t t = b + lane; t < e; t += 64) {
-      const float *v = V + (int64_t)col[t] * K;
+      const int j = col[t];
+      if (j < 0 || j >= n) continue;
+      const float *v = V + (int64_t)j * K;
       float p = 0.f;
 #pragma unroll
       for (int a = 0; a < K; ++a) p = __builtin_fmaf(u[a], v[a], p);
@@ -282,12 +278,10 @@ static open_status objective_impl(open_ctx *ctx, int64_t m, int n, const int64_t
   void *part;
   open_status st;
   if ((st = ws_get(ctx, open_ctx::WS_MISC, sizeof(double) * (kRedBlocks + 8), &part))) return st;
-  hipLaunchKernelGGL(k_objective_rows<K>, dim3(kRedBlocks), dim3(256), 0, ctx->stream, m, row_ptr, col, val, U, V,
-                     lambda, weighted, (double *)part);
-  OPEN_LAUNCH_CHECK(ctx);
-  hipLaunchKernelGGL(k_objective_cols<K>, dim3(1), dim3(256), 0, ctx->stream, n, col_ptr, V, lambda, weighted,
-                     (const double *)part, kRedBlocks, out_dev);
-  OPEN_LAUNCH_CHECK(ctx);
+  OPEN_LAUNCH(ctx, "objective_rows", k_objective_rows<K>, dim3(kRedBlocks), dim3(256), 0, m, n, row_ptr, col, val, U, V,
+              lambda, weighted, (double *)part);
+  OPEN_LAUNCH(ctx, "objective_cols", k_objective_cols<K>, dim3(1), dim3(256), 0, n, col_ptr, V, lambda, weighted,
+              (const double *)part, kRedBlocks, out_dev);
   return OPEN_OK;
 }
 
@@ -323,7 +317,7 @@ open_status open_csr_to_csc(open_ctx *ctx, int64_t m, int32_t n, const int64_t *
   }
   open_status st = check_cols(ctx, nnz, col, n);
   if (st) return st;
-  return csr_to_csc_impl(ctx, m, n, row_ptr, col, val, col_ptr, row_idx, cval);
+  return csr_to_csc_dev(ctx, m, n, row_ptr, col, val, col_ptr, row_idx, cval);
 }
 
 open_status open_objective(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64_t *row_ptr,
@@ -344,7 +338,7 @@ open_status open_objective(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const
   if ((st = ws_get(ctx, open_ctx::WS_CSC_PTR, sizeof(int64_t) * (n + 1), &cp))) return st;
   if ((st = ws_get(ctx, open_ctx::WS_CSC_IDX, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1), &ri))) return st;
   if ((st = ws_get(ctx, open_ctx::WS_CSC_VAL, sizeof(float) * (size_t)(nnz > 0 ? nnz : 1), &cv))) return st;
-  if ((st = csr_to_csc_impl(ctx, m, n, row_ptr, col, val, (int64_t *)cp, (int32_t *)ri, (float *)cv))) return st;
+  if ((st = csr_to_csc_dev(ctx, m, n, row_ptr, col, val, (int64_t *)cp, (int32_t *)ri, (float *)cv))) return st;
   double *h;
   if ((st = pinned_get(ctx, 64, (void **)&h))) return st;
   void *d;
@@ -370,12 +364,11 @@ open_status open_residual(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const 
   if (blocks > ctx->num_cu * 8) blocks = ctx->num_cu * 8;
   const dim3 g((unsigned)blocks), b(256);
   switch (k) {
-    case 8: hipLaunchKernelGGL(k_residual<8>, g, b, 0, ctx->stream, m, row_ptr, col, val, U, V, rho); break;
-    case 16: hipLaunchKernelGGL(k_residual<16>, g, b, 0, ctx->stream, m, row_ptr, col, val, U, V, rho); break;
-    case 32: hipLaunchKernelGGL(k_residual<32>, g, b, 0, ctx->stream, m, row_ptr, col, val, U, V, rho); break;
-    default: hipLaunchKernelGGL(k_residual<64>, g, b, 0, ctx->stream, m, row_ptr, col, val, U, V, rho); break;
+    case 8: OPEN_LAUNCH(ctx, "residual", k_residual<8>, g, b, 0, m, n, row_ptr, col, val, U, V, rho); break;
+    case 16: OPEN_LAUNCH(ctx, "residual", k_residual<16>, g, b, 0, m, n, row_ptr, col, val, U, V, rho); break;
+    case 32: OPEN_LAUNCH(ctx, "residual", k_residual<32>, g, b, 0, m, n, row_ptr, col, val, U, V, rho); break;
+    default: OPEN_LAUNCH(ctx, "residual", k_residual<64>, g, b, 0, m, n, row_ptr, col, val, U, V, rho); break;
   }
-  OPEN_LAUNCH_CHECK(ctx);
   return OPEN_OK;
 }
 
@@ -424,7 +417,7 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
   }
   do {
     if ((st = check_cols(ctx, nnz, col, n))) break;
-    if ((st = csr_to_csc_impl(ctx, m, n, row_ptr, col, val, cp, ri, cv))) break;
+    if ((st = csr_to_csc_dev(ctx, m, n, row_ptr, col, val, cp, ri, cv))) break;
     int32_t *l;
     int64_t *c;
     if ((st = bucket_rows(ctx, m, row_ptr, k, &l, &c, INT64_MAX))) break;

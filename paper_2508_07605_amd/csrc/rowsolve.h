@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_solve_tier(const float *__restrict__ F,
 
 // Launch one tier kernel (classes c_lo..c_hi) with a persistent grid sized for m rows.
 template <int K, int NLO, int NHI, bool DUAL>
-open_status launch_tier(open_ctx *ctx, const float *F, int n, const int64_t *ptr, const int32_t *idx, const float *val,
+open_status launch_tier(const char *name, open_ctx *ctx, const float *F, int n, const int64_t *ptr, const int32_t *idx, const float *val,
                         float lambda, int weighted, const int32_t *list, const int64_t *cls, int c_lo, int c_hi,
                         float *X, int32_t *status, int64_t m) {
   const int64_t groups = (m + 15) / 16;
@@ -232,9 +232,8 @@ open_status launch_tier(open_ctx *ctx, const float *F, int n, const int64_t *ptr
   const int64_t cap = (int64_t)ctx->num_cu * 4;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_solve_tier<K, NLO, NHI, DUAL>), dim3((unsigned)blocks), dim3(256), 0, ctx->stream, F, n,
-                     ptr, idx, val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
-  OPEN_LAUNCH_CHECK(ctx);
+  OPEN_LAUNCH(ctx, name, (k_solve_tier<K, NLO, NHI, DUAL>), dim3((unsigned)blocks), dim3(256), 0, F, n, ptr, idx, val,
+              list, cls, c_lo, c_hi, lambda, weighted, X, status);
   return OPEN_OK;
 }
 

@@ -4,7 +4,7 @@
 namespace openk {
 
 open_status tier_k32_d56(OPEN_TIER_ARGS) {
-  return launch_tier<32, 5, 6, true>(OPEN_TIER_PASS, 5, 6, X, status, m);
+  return launch_tier<32, 5, 6, true>("ridge_k32_d56", OPEN_TIER_PASS, 5, 6, X, status, m);
 }
 
 }  // namespace openk

@@ -4,7 +4,7 @@
 namespace openk {
 
 open_status tier_k32_d78(OPEN_TIER_ARGS) {
-  return launch_tier<32, 7, 8, true>(OPEN_TIER_PASS, 7, 8, X, status, m);
+  return launch_tier<32, 7, 8, true>("ridge_k32_d78", OPEN_TIER_PASS, 7, 8, X, status, m);
 }
 
 }  // namespace openk

@@ -4,7 +4,7 @@
 namespace openk {
 
 open_status tier_k32_primal(OPEN_TIER_ARGS) {
-  return launch_tier<32, 8, 8, false>(OPEN_TIER_PASS, 9, 15, X, status, m);
+  return launch_tier<32, 8, 8, false>("ridge_k32_primal", OPEN_TIER_PASS, 9, 15, X, status, m);
 }
 
 }  // namespace openk

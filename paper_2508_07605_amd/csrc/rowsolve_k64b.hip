@@ -4,7 +4,7 @@
 namespace openk {
 
 open_status tier_k64_d56(OPEN_TIER_ARGS) {
-  return launch_tier<64, 5, 6, true>(OPEN_TIER_PASS, 5, 6, X, status, m);
+  return launch_tier<64, 5, 6, true>("ridge_k64_d56", OPEN_TIER_PASS, 5, 6, X, status, m);
 }
 
 }  // namespace openk

@@ -4,7 +4,7 @@
 namespace openk {
 
 open_status tier_k64_d78(OPEN_TIER_ARGS) {
-  return launch_tier<64, 7, 8, true>(OPEN_TIER_PASS, 7, 8, X, status, m);
+  return launch_tier<64, 7, 8, true>("ridge_k64_d78", OPEN_TIER_PASS, 7, 8, X, status, m);
 }
 
 }  // namespace openk

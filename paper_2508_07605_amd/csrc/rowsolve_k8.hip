@@ -4,11 +4,11 @@
 namespace openk {
 
 open_status tier_k8_dual(OPEN_TIER_ARGS) {
-  return launch_tier<8, 1, 2, true>(OPEN_TIER_PASS, 0, 2, X, status, m);
+  return launch_tier<8, 1, 2, true>("ridge_k8_dual", OPEN_TIER_PASS, 0, 2, X, status, m);
 }
 
 open_status tier_k8_primal(OPEN_TIER_ARGS) {
-  return launch_tier<8, 2, 2, false>(OPEN_TIER_PASS, 9, 15, X, status, m);
+  return launch_tier<8, 2, 2, false>("ridge_k8_primal", OPEN_TIER_PASS, 9, 15, X, status, m);
 }
 
 }  // namespace openk

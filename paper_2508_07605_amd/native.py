@@ -30,6 +30,8 @@ SIGNATURES = {
     "open_set_stream": (_I32, [_P, _P]),
     "open_last_error": (ctypes.c_char_p, [_P]),
     "open_sync": (_I32, [_P]),
+    "open_profile": (_I32, [_P, _I32]),
+    "open_profile_read": (_I32, [_P, _P, _P, _P, _I32, _I32]),
     "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_csr_to_csc": (_I32, [_P, _I64, _I32, _P, _P, _P, _P, _P, _P]),
     "open_fit": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
@@ -115,6 +117,20 @@ class Context:
 
     def sync(self):
         self.check(lib().open_sync(self.handle))
+
+    def profile(self, enable=True):
+        self.check(lib().open_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self, reset=True):
+        """{kernel name: (total ms, launches)} since the last reset."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        tot = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        n = lib().open_profile_read(self.handle, names, tot, cnt, cap, int(bool(reset)))
+        if n < 0:
+            raise OpenError(OPEN_E_DEVICE, "open_profile_read failed")
+        return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(n, cap))}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -172,16 +172,6 @@ def draw_rows(cfg_id: int, grid: Grid, m: int, count_spec, seed: int = 0, noise:
     return Rows(apps, row_ptr, col, val)
 
 
-def transpose_csr(row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray, n: int):
-    """CSR -> CSC of the same entries (used to hand tests a column view)."""
-    m = len(row_ptr) - 1
-    rows = np.repeat(np.arange(m, dtype=np.int32), np.diff(row_ptr))
-    order = np.lexsort((rows, col))
-    col_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(np.bincount(col, minlength=n), out=col_ptr[1:])
-    return col_ptr, rows[order], val[order]
-
-
 # ----------------------------------------------------------------------------- factors
 def init_factors(cfg_id: int, m: int, n: int, k: int, std: float = 0.1, seed: int = 0):
     """Initial U0 (m x k) and V0 (n x k), iid N(0, std^2), float32."""
@@ -253,3 +243,18 @@ def tiny_problem(seed: int = 0):
                       np.concatenate([dense.apps.gg, new.apps.gg])),
                  rp, np.concatenate([dense.col, new.col]), np.concatenate([dense.val, new.val]))
     return grid, dense, new, union
+
+
+def latent_rows(cfg_id: int, grid: Grid, V: np.ndarray, m: int, seed: int = 0, n_proto: int = 4096,
+                noise: float = 0.01) -> np.ndarray:
+    """Application factors (m x k, float32) whose predictions u . v_s look like normalized
+    performance: n_proto prototype apps are projected (least squares) from their noiseless
+    truth rows onto the setting factors V, and every row is a prototype plus N(0, noise^2)."""
+    apps = draw_apps(rng(cfg_id, S_EVAL, seed), n_proto)
+    T = truth_dense(apps, grid)
+    Vd = V.astype(np.float64)
+    proto = np.linalg.lstsq(Vd, T.T, rcond=None)[0].T  # n_proto x k
+    r = rng(cfg_id, S_EVAL, seed + 1)
+    pick = r.integers(0, n_proto, size=m)
+    U = proto[pick] + noise * r.standard_normal((m, V.shape[1]))
+    return np.ascontiguousarray(U.astype(np.float32))
