@@ -40,20 +40,17 @@ def row_flops(n, k):
     return np.where(n == 0, 0.0, np.where(dual, dual_flops(n, k), primal_flops(n, k)))
 
 
-def tier_of_counts(n, k):
-    """Name of the ridge kernel that solves a row with n observations (matches the library)."""
+def kernel_of_counts(n, k):
+    """Name of the ridge kernel that solves a row with n observations (matches the library):
+    dual rows of n <= min(k, 32) go to the kernel of padded dimension 4 ceil(n/4), longer rows
+    to the primal kernel."""
     import numpy as np
     n = np.asarray(n)
-    out = np.empty(n.shape, dtype=object)
     dmax = min(k, 32)
-    out[n <= 16] = "d14"
-    out[(n > 16) & (n <= 24)] = "d56"
-    out[(n > 24) & (n <= dmax)] = "d78"
-    out[n > dmax] = "primal"
-    if k == 8:
-        out[n <= 8] = "dual"
-    if k == 16:
-        out[n <= 16] = "dual"
+    d = np.maximum(4, 4 * ((n + 3) // 4))
+    names = np.array(["ridge_k%d_d%d" % (k, x) for x in range(0, 33)], dtype=object)
+    out = names[np.minimum(d, 32)]
+    out[n > dmax] = "ridge_k%d_primal" % k
     return out
 
 
@@ -131,7 +128,7 @@ def main():
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
     counts = rows.counts()
-    tiers = tier_of_counts(counts, k)
+    tiers = kernel_of_counts(counts, k)
     flops = row_flops(counts, k)
     kernels = {}
     for name, (tot, launches) in prof.items():
@@ -139,8 +136,7 @@ def main():
         kernels[name] = avg_ms
     ridge = {n: t for n, t in kernels.items() if n.startswith("ridge_")}
     dom = max(ridge, key=ridge.get)
-    tier = dom.split("_")[-1]
-    sel = tiers == tier
+    sel = tiers == dom
     dom_flops = float(flops[sel].sum())
     dom_rows = int(sel.sum())
     dom_bytes = float((8 * counts[sel] + 8 + 4 * k).sum())

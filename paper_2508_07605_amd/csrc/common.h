@@ -30,17 +30,36 @@ __device__ __forceinline__ float quad_bcast(float x, int src) {
 }
 template <int SRC>
 __device__ __forceinline__ float quad_bcast_c(float x) {
-  return __builtin_amdgcn_update_dpp(0.0f, x, SRC * 0x55, 0xf, 0xf, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), SRC * 0x55, 0xf, 0xf, true));
 }
 // partner lane q^1 and q^2 within the quad
 __device__ __forceinline__ float quad_xor1(float x) {
-  return __builtin_amdgcn_update_dpp(0.0f, x, 0xb1, 0xf, 0xf, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xb1, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float quad_xor2(float x) {
-  return __builtin_amdgcn_update_dpp(0.0f, x, 0x4e, 0xf, 0xf, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4e, 0xf, 0xf, true));
 }
-__device__ __forceinline__ int quad_xor1_i(int x) { return __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false); }
-__device__ __forceinline__ int quad_xor2_i(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false); }
+__device__ __forceinline__ int quad_xor1_i(int x) { return __builtin_amdgcn_mov_dpp(x, 0xb1, 0xf, 0xf, true); }
+__device__ __forceinline__ int quad_xor2_i(int x) { return __builtin_amdgcn_mov_dpp(x, 0x4e, 0xf, 0xf, true); }
+
+// ---------------------------------------------------------------- bounds-checked loads
+// Raw buffer loads: an offset at or beyond the buffer's byte size (negative offsets wrap to
+// large unsigned values) returns zero instead of touching memory, so padded and invalid
+// entries need no branch.  Word 3 is the gfx9-family raw-buffer format.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint64_t bytes) {
+  const int nrec = bytes >= 0xffffffffull ? (int)0xffffffff : (int)(uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, nrec, 0x00020000);
+}
+__device__ __forceinline__ float bload_f32(__amdgpu_buffer_rsrc_t r, int off_bytes) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off_bytes, 0, 0));
+}
+__device__ __forceinline__ int bload_i32(__amdgpu_buffer_rsrc_t r, int off_bytes) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off_bytes, 0, 0);
+}
+__device__ __forceinline__ f4 bload_f4(__amdgpu_buffer_rsrc_t r, int off_bytes) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off_bytes, 0, 0));
+}
 
 // 16 independent 4x4 outer products: lanes 4b..4b+3 form block b; block b accumulates
 // D_b[i][j] += A_b[i] * B_b[j] with A_b[i] from lane 4b+i and B_b[j] from lane 4b+j.

@@ -5,253 +5,459 @@
 //   dual    (n_i <= k): (F_O F_O^T + lambda w I_n) a = r,   u = F_O^T a
 // (the same u by the push-through identity; w = n_i or 1).
 //
-// Layout: a wavefront solves 16 systems at once, four lanes per system ("quad").  A system
-// of dimension D = 4N is stored as N x N tiles of 4x4; only tiles (I >= J) are kept.  Lane q
-// of a quad holds, for every tile (I, J), column 4J+q of that tile (rows 4I..4I+3), which is
-// exactly the output layout of v_mfma_f32_4x4x1_16b: block b of that instruction is quad b.
-//   Gram    one 4x4x1 MFMA per tile and per contraction index (latent index for the dual
-//           form, observation for the primal form); FP32 inputs, FP32 accumulation.
-//   Solve   symmetric Gaussian elimination without pivoting (LDL^T, valid for SPD
-//           matrices), the forward substitution fused into it, then column-oriented back
-//           substitution.  Column p is broadcast inside the quad with DPP quad_perm.
-//   Output  dual: u = F_O^T a, partial sums per lane, quad all-reduce with DPP;
-//           primal: lane q holds u[4J+q] directly.
-// Padded rows of a dual system (i >= n_i) have zero factors, unit diagonal and zero rhs,
-// so their unknowns are exactly zero and do not touch the others.
+// One persistent kernel per size class.  A wavefront solves a group of 64/P systems of one
+// class, P lanes per system (P = 1, 2 or 4), padded dimension D.
+//
+//   Stage  A persistent block copies the factor matrix F into LDS once when it fits (the
+//          fold-in's 480 x 32 setting factors do); every factor-row gather then reads LDS.
+//          Each lane fetches the column indices and values of its own system once per group
+//          and shares them with the other lanes through LDS.
+//   Gram   In sub-batches of 16 systems (quad b of the wave = system b of the sub-batch) the
+//          system is kept as 4x4 tiles (lower block triangle only): one 4x4x1 MFMA
+//          (v_mfma_f32_4x4x1_16b) per tile and contraction index - the latent index for the
+//          dual form, the observation for the primal form.  FP32 inputs and accumulation.
+//          The instruction's output puts column 4J+q of tile (I, J) in lane q of the quad.
+//   Layout The P lanes of a system own its columns interleaved: lane pi owns c = P m + pi and
+//          keeps rows P m .. D-1 of them in registers.  For P = 4 that is exactly the MFMA
+//          output; for P < 4 the lower triangle passes through a per-wave LDS buffer.
+//   Solve  Right-looking symmetric Gaussian elimination (LDL^T, no pivoting: the systems are
+//          SPD) with the forward substitution fused in, then a column-oriented back
+//          substitution.  Pivot columns move between the P lanes by DPP quad_perm; with
+//          P = 1 no data moves at all.
+//   Output dual: each lane forms K/P outputs of u = F_O^T a from its system's factor rows;
+//          primal: the solution is u itself.
+// Padded rows of a dual system (i >= n_i) have zero factors, unit diagonal and zero rhs:
+// their unknowns are exactly zero and they do not touch the others.
 #pragma once
 #include "common.h"
 
 namespace openk {
 
-template <int N, int K, bool DUAL>
-__device__ __forceinline__ void solve16(const float *__restrict__ F, int n, const int64_t *__restrict__ ptr,
-                                        const int32_t *__restrict__ idx, const float *__restrict__ val, int64_t row,
-                                        float lambda, int weighted, float *__restrict__ X,
-                                        int32_t *__restrict__ status) {
-  constexpr int T = N * (N + 1) / 2;
-  constexpr int D = 4 * N;
-  static_assert(DUAL || D == K, "primal systems are k x k");
-  const int q = threadIdx.x & 3;
-  int64_t beg = 0;
-  int cnt = 0;
-  if (row >= 0) {
-    beg = ptr[row];
-    cnt = (int)(ptr[row + 1] - beg);
+// DPP broadcast of lane `src` of each group of P lanes (P = 1, 2, 4) inside the quad
+template <int P, int SRC>
+__device__ __forceinline__ float grp_bcast(float x) {
+  if constexpr (P == 1) {
+    return x;
+  } else if constexpr (P == 2) {
+    constexpr int c = SRC | (SRC << 2) | ((2 + SRC) << 4) | ((2 + SRC) << 6);
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), c, 0xf, 0xf, true));
+  } else {
+    return quad_bcast_c<SRC>(x);
   }
-  f4 acc[T];
-  sfor<0, T>([&](auto t) { acc[t] = f4{0.f, 0.f, 0.f, 0.f}; });
-  float b[N];
-  int nonfinite = 0, badidx = 0;
-  int oi[DUAL ? N : 1];
+}
 
+// v[pi] for the lane's position pi in its group (compile-time array, runtime pi)
+template <int P>
+__device__ __forceinline__ float pick(const float *v, int pi) {
+  if constexpr (P == 1) return v[0];
+  if constexpr (P == 2) return pi ? v[1] : v[0];
+  return pi == 0 ? v[0] : pi == 1 ? v[1] : pi == 2 ? v[2] : v[3];
+}
+
+// ---------------------------------------------------------------- factor-row access
+// F rows from LDS or from global memory through a bounds-checked buffer resource.  In LDS
+// the 16-byte chunks of row j are stored in the order c ^ (j mod K/4), so lanes reading the
+// same chunk of different rows hit different banks.  A row index of -1 reads as zeros.
+template <int K, bool LDS>
+struct FRows {
+  static constexpr int CH = K / 4;  // 16-byte chunks per row
+  const float *lds;
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ static __forceinline__ int slot(int j, int c) { return j * K + 4 * (c ^ (j & (CH - 1))); }
+  __device__ __forceinline__ f4 row4(int j, int k0) const {
+    if constexpr (LDS) {
+      const int jj = j >= 0 ? j : 0;
+      const f4 v = *reinterpret_cast<const f4 *>(lds + slot(jj, k0 / 4));
+      return j >= 0 ? v : f4{0.f, 0.f, 0.f, 0.f};
+    } else {
+      return bload_f4(rs, (j * K + k0) * 4);
+    }
+  }
+  __device__ __forceinline__ float row1(int j, int k) const {
+    if constexpr (LDS) {
+      const int jj = j >= 0 ? j : 0;
+      const float v = lds[slot(jj, k / 4) + (k & 3)];
+      return j >= 0 ? v : 0.f;
+    } else {
+      return bload_f32(rs, (j * K + k) * 4);
+    }
+  }
+};
+
+// LDS per wave (floats): lower triangles of one sub-batch (P < 4), the group's column
+// indices and values, and per-system bookkeeping
+__host__ __device__ constexpr int tri_stride(int D) { return (D * (D + 1) / 2) | 1; }
+__host__ __device__ constexpr int wave_lds_floats(int P, int D) {
+  return (P < 4 ? 16 * tri_stride(D) : 0) + 2 * (64 / P) * (D + 1);
+}
+
+template <int P, int D, int K, bool DUAL, bool LDSF>
+__device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, const int64_t *__restrict__ ptr,
+                                            const int32_t *__restrict__ idx, const float *__restrict__ val,
+                                            const int32_t *__restrict__ list, int64_t slot0, int64_t end,
+                                            float lambda, int weighted, float *__restrict__ X,
+                                            int32_t *__restrict__ status, float *__restrict__ wl) {
+  constexpr int N = D / 4;            // tiles per dimension
+  constexpr int T = N * (N + 1) / 2;  // lower block triangle
+  constexpr int M = D / P;            // columns owned per lane
+  constexpr int SB = 4 / P;           // sub-batches of 16 systems
+  constexpr int SYS = 64 / P;         // systems per wave
+  constexpr int ST = tri_stride(D);
+  constexpr int E = D + 1;            // LDS pitch of a system's index/value lists
+  static_assert(D % 4 == 0 && D % P == 0, "shape");
+  static_assert(DUAL || D == K, "primal systems are k x k");
+  const int lane = threadIdx.x & 63;
+  const int pi = lane % P;  // position in the system's lane group
+  const int qi = lane & 3;  // position in the quad (MFMA layout)
+  const int sme = lane / P;  // this lane's system in the group
+  float *tri_buf = wl;                                       // [16][ST]      (P < 4)
+  int *ixs = reinterpret_cast<int *>(wl + (P < 4 ? 16 * ST : 0));  // [SYS][E] column indices (-1 = none)
+  float *vxs = wl + (P < 4 ? 16 * ST : 0) + SYS * E;               // [SYS][E] values
+
+  // ---- this lane's system: row, count, flags; its index/value lists into LDS
+  const int64_t myslot = slot0 + sme;
+  const int64_t my_row = myslot < end ? (int64_t)list[myslot] : -1;
+  const int64_t mrr = my_row >= 0 ? my_row : 0;
+  const int64_t mbeg = ptr[mrr];
+  const int my_cnt = my_row >= 0 ? (int)(ptr[mrr + 1] - mbeg) : 0;
+  int my_flags = 0;  // 1: non-finite value, 2: column index out of range
   if constexpr (DUAL) {
-    sfor<0, N>([&](auto J) {
-      const int i = 4 * J + q;
-      const bool ok = i < cnt;
-      int j = ok ? idx[beg + i] : -1;
-      if (ok && (j < 0 || j >= n)) {
-        badidx = 1;
-        j = -1;
+    // lane pi of the group fetches entries pi, pi + P, ...
+    const bool any_obs = __any(my_cnt > 0);
+    sfor<0, M>([&](auto Mm) {
+      const int i = P * Mm + pi;
+      const bool ok = i < my_cnt;
+      const int64_t e = ok ? mbeg + i : 0;
+      int j = -1;
+      float r = 0.f;
+      if (any_obs) {
+        j = idx[e];
+        r = val[e];
       }
-      oi[J] = j;
-      const float r = ok ? val[beg + i] : 0.f;
-      b[J] = r;
-      nonfinite |= !__builtin_isfinite(r);
+      if (ok && (j < 0 || j >= n)) my_flags |= 2;
+      if (ok && !__builtin_isfinite(r)) my_flags |= 1;
+      ixs[sme * E + i] = (ok && j >= 0 && j < n) ? j : -1;
+      vxs[sme * E + i] = ok ? r : 0.f;
     });
-    nonfinite |= quad_xor1_i(nonfinite);
-    nonfinite |= quad_xor2_i(nonfinite);
-    badidx |= quad_xor1_i(badidx);
-    badidx |= quad_xor2_i(badidx);
-    // Gram of the observed factor rows over the latent index
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      f4 a[N];
-      sfor<0, N>([&](auto J) {
-        a[J] = oi[J] >= 0 ? *reinterpret_cast<const f4 *>(F + (int64_t)oi[J] * K + k0) : f4{0.f, 0.f, 0.f, 0.f};
-      });
-      sfor<0, 4>([&](auto kk) {
-        sfor<0, N>([&](auto I) {
-          sfor<0, I + 1>([&](auto J) {
-            acc[tri(I, J)] = mfma4x4(a[I][(int)kk], a[J][(int)kk], acc[tri(I, J)]);
+    if constexpr (P == 2) my_flags |= __builtin_amdgcn_mov_dpp(my_flags, 0xb1, 0xf, 0xf, true);
+    if constexpr (P == 4) {
+      my_flags |= quad_xor1_i(my_flags);
+      my_flags |= quad_xor2_i(my_flags);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // owned columns: st[m][j] = G[P m + j][P m + pi], j = 0 .. D - P m - 1
+  float st[M][D];
+  float pb[DUAL ? 1 : N];  // primal rhs in the quad layout: pb[J] = (F_O^T r)[4J + qi]
+  int pflags = 0;
+  if constexpr (!DUAL) sfor<0, N>([&](auto J) { pb[J] = 0.f; });
+
+#pragma unroll 1
+  for (int sb = 0; sb < SB; ++sb) {
+    // ---- quad b of the wave works on system qs = 16 sb + b (quad-layout view)
+    const int qs = 16 * sb + (lane >> 2);
+    const int qsrc = qs * P;  // a lane of that system (holds its count)
+    const int cnt = __shfl(my_cnt, qsrc, 64);
+    f4 acc[T];
+    sfor<0, T>([&](auto t) { acc[t] = f4{0.f, 0.f, 0.f, 0.f}; });
+    if constexpr (DUAL) {
+      int oi[N];
+      sfor<0, N>([&](auto J) { oi[J] = ixs[qs * E + 4 * J + qi]; });
+      sfor<0, K / 4>([&](auto C) {
+        constexpr int k0 = 4 * C;
+        f4 a[N];
+        sfor<0, N>([&](auto J) { a[J] = Fr.row4(oi[J], k0); });
+        sfor<0, 4>([&](auto kk) {
+          sfor<0, N>([&](auto I) {
+            sfor<0, I + 1>([&](auto J) {
+              acc[tri(I, J)] = mfma4x4(a[I][(int)kk], a[J][(int)kk], acc[tri(I, J)]);
+            });
           });
         });
       });
-    }
-  } else {
-    sfor<0, N>([&](auto J) { b[J] = 0.f; });
-    // Gram of the observed factor rows over the observations (all 16 systems step together)
-    const int tmax = wave_max_i(cnt);
-    for (int t = 0; t < tmax; ++t) {
-      bool ok = t < cnt;
-      int j = ok ? idx[beg + t] : 0;
-      if (ok && (j < 0 || j >= n)) {
-        badidx = 1;
-        ok = false;
+    } else {
+      // primal: contraction over the observations of the 16 systems, in step
+      const int64_t qrow = __shfl((int)(my_row & 0xffffffff), qsrc, 64) |
+                           ((int64_t)__shfl((int)(my_row >> 32), qsrc, 64) << 32);
+      const int64_t qbeg = qrow >= 0 ? ptr[qrow] : 0;
+      const int tmax = wave_max_i(cnt);
+      int jn = 0;
+      float rn = 0.f;
+      if (tmax > 0) {
+        jn = idx[cnt > 0 ? qbeg : 0];
+        rn = val[cnt > 0 ? qbeg : 0];
       }
-      const float r = ok ? val[beg + t] : 0.f;
-      nonfinite |= !__builtin_isfinite(r);
-      float a[N];
-      sfor<0, N>([&](auto J) { a[J] = ok ? F[(int64_t)j * K + 4 * J + q] : 0.f; });
-      sfor<0, N>([&](auto I) {
-        sfor<0, I + 1>([&](auto J) { acc[tri(I, J)] = mfma4x4(a[I], a[J], acc[tri(I, J)]); });
-      });
-      sfor<0, N>([&](auto J) { b[J] = __builtin_fmaf(r, a[J], b[J]); });
+      for (int t = 0; t < tmax; ++t) {
+        int j = jn;
+        const float r0 = rn;
+        if (t + 1 < tmax) {
+          const int64_t e = t + 1 < cnt ? qbeg + t + 1 : (cnt > 0 ? qbeg : 0);
+          jn = idx[e];
+          rn = val[e];
+        }
+        const bool ok = t < cnt;
+        if (ok && (j < 0 || j >= n)) pflags |= 2;
+        if (ok && !__builtin_isfinite(r0)) pflags |= 1;
+        j = (ok && j >= 0 && j < n) ? j : -1;
+        const float r = j >= 0 ? r0 : 0.f;
+        float a[N];
+        sfor<0, N>([&](auto J) { a[J] = Fr.row1(j, 4 * J + qi); });
+        sfor<0, N>([&](auto I) {
+          sfor<0, I + 1>([&](auto J) { acc[tri(I, J)] = mfma4x4(a[I], a[J], acc[tri(I, J)]); });
+        });
+        sfor<0, N>([&](auto J) { pb[J] = __builtin_fmaf(r, a[J], pb[J]); });
+      }
     }
-  }
-
-  // ridge term on the diagonal (unit diagonal on padded rows of a dual system)
-  const float reg = lambda * (weighted ? (float)cnt : 1.0f);
-  sfor<0, N>([&](auto J) {
-    const int c = 4 * J + q;
-    const float dg = (!DUAL || c < cnt) ? reg : 1.0f;
-    sfor<0, 4>([&](auto v) { acc[tri(J, J)][(int)v] += (q == (int)v) ? dg : 0.f; });
-  });
-
-  // elimination with fused forward substitution; column p is broadcast one row block at a time
-  int bad = 0;
-  sfor<0, D>([&](auto P) {
-    constexpr int p = decltype(P)::value, Jp = p >> 2, qp = p & 3;
-    const float d = quad_bcast_c<qp>(acc[tri(Jp, Jp)][qp]);
-    bad |= !(d > 0.f);
-    const float s = __builtin_amdgcn_rcpf(d);
-    const float bp = quad_bcast_c<qp>(b[Jp]);
-    float lc[N];
-    sfor<Jp, N>([&](auto II) {
-      constexpr int I = decltype(II)::value;
-      float w[4];
-      sfor<0, 4>([&](auto V) {
-        constexpr int v = decltype(V)::value;
-        if constexpr (4 * I + v > p)
-          w[v] = quad_bcast_c<qp>(acc[tri(I, Jp)][v]);
-        else
-          w[v] = 0.f;
-      });
-      // multiplier of the lane's own column c = 4I+q:  G[c][p] / d  (0 for c <= p)
-      lc[I] = (q == 0 ? w[0] : q == 1 ? w[1] : q == 2 ? w[2] : w[3]) * s;
-      b[I] = __builtin_fmaf(-lc[I], bp, b[I]);
-      sfor<Jp, I + 1>([&](auto JJ) {
-        constexpr int Jc = decltype(JJ)::value;
-        sfor<0, 4>([&](auto V) {
-          constexpr int v = decltype(V)::value;
-          if constexpr (4 * I + v > p) acc[tri(I, Jc)][v] = __builtin_fmaf(-w[v], lc[Jc], acc[tri(I, Jc)][v]);
+    // ridge term (unit diagonal on padded rows of a dual system)
+    const float reg = lambda * (weighted ? (float)cnt : 1.0f);
+    sfor<0, N>([&](auto J) {
+      const int c = 4 * J + qi;
+      const float dg = (!DUAL || c < cnt) ? reg : 1.0f;
+      sfor<0, 4>([&](auto v) { acc[tri(J, J)][(int)v] += (qi == (int)v) ? dg : 0.f; });
+    });
+    if constexpr (P == 4) {
+      // the MFMA layout already is the owned-column layout
+      sfor<0, M>([&](auto m) {
+        sfor<0, D>([&](auto j) {
+          constexpr int r = 4 * decltype(m)::value + decltype(j)::value;
+          if constexpr (r < D) st[m][j] = acc[tri(r / 4, decltype(m)::value)][r % 4];
         });
       });
-    });
-  });
-
-  // back substitution
-  float x[N], dotv[N];
-  sfor<0, N>([&](auto J) {
-    x[J] = 0.f;
-    dotv[J] = 0.f;
-  });
-  sfor_down<0, D>([&](auto P) {
-    constexpr int p = decltype(P)::value, Jp = p >> 2, qp = p & 3;
-    const float d = quad_bcast_c<qp>(acc[tri(Jp, Jp)][qp]);
-    const float xo = (b[Jp] - dotv[Jp]) * __builtin_amdgcn_rcpf(d);
-    const float xp = quad_bcast_c<qp>(xo);
-    x[Jp] = (q == qp) ? xp : x[Jp];
-    sfor<0, Jp + 1>([&](auto Jc) { dotv[Jc] = __builtin_fmaf(acc[tri(Jp, Jc)][qp], xp, dotv[Jc]); });
-  });
-
-  const bool good = row >= 0 && cnt > 0 && !bad && !nonfinite && !badidx;
-  if constexpr (DUAL) {
-    // u = F_O^T a, four outputs at a time; lane q stores output k0 + q
-    sfor<0, K / 4>([&](auto C) {
-      constexpr int k0 = 4 * C;
-      f4 uo = {0.f, 0.f, 0.f, 0.f};
-      sfor<0, N>([&](auto J) {
-        const f4 f = oi[J] >= 0 ? *reinterpret_cast<const f4 *>(F + (int64_t)oi[J] * K + k0) : f4{0.f, 0.f, 0.f, 0.f};
-        sfor<0, 4>([&](auto e) { uo[(int)e] = __builtin_fmaf(x[J], f[(int)e], uo[(int)e]); });
+    } else {
+      // lower triangle of each system to LDS, then the system's P lanes read their columns
+      float *sys = tri_buf + (lane >> 2) * ST;
+      sfor<0, N>([&](auto I) {
+        sfor<0, I + 1>([&](auto J) {
+          sfor<0, 4>([&](auto v) {
+            const int r = 4 * I + (int)v, c = 4 * J + qi;
+            if (r >= c) sys[r * (r + 1) / 2 + c] = acc[tri(I, J)][(int)v];
+          });
+        });
       });
-      sfor<0, 4>([&](auto e) {
-        uo[(int)e] += quad_xor1(uo[(int)e]);
-        uo[(int)e] += quad_xor2(uo[(int)e]);
-      });
-      if (row >= 0) {
-        const float o = q == 0 ? uo[0] : q == 1 ? uo[1] : q == 2 ? uo[2] : uo[3];
-        X[row * K + k0 + q] = good ? o : 0.f;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (sme / 16 == sb) {
+        const float *mine = tri_buf + (sme % 16) * ST;
+        sfor<0, M>([&](auto m) {
+          sfor<0, D>([&](auto j) {
+            constexpr int mm = decltype(m)::value, jj = decltype(j)::value;
+            if constexpr (P * mm + jj < D) {
+              const int r = P * mm + jj, c = P * mm + pi;
+              const int hi = r > c ? r : c, lo = r > c ? c : r;
+              st[mm][jj] = mine[hi * (hi + 1) / 2 + lo];
+            }
+          });
+        });
       }
-    });
-  } else {
-    if (row >= 0) sfor<0, N>([&](auto J) { X[row * K + 4 * J + q] = good ? x[J] : 0.f; });
-  }
-  if (status && row >= 0 && q == 0)
-    status[row] = cnt == 0      ? OPEN_ROW_EMPTY
-                  : badidx    ? OPEN_ROW_BADINDEX
-                  : nonfinite ? OPEN_ROW_NONFINITE
-                  : bad       ? OPEN_ROW_NONPOS_PIVOT
-                              : OPEN_ROW_OK;
-}
-
-template <int K, int N, int NHI>
-__device__ __forceinline__ void dispatch_dual(int nmax, const float *F, int n, const int64_t *ptr, const int32_t *idx,
-                                              const float *val, int64_t row, float lambda, int weighted, float *X,
-                                              int32_t *status) {
-  if constexpr (N < NHI) {
-    if (nmax <= 4 * N) {
-      solve16<N, K, true>(F, n, ptr, idx, val, row, lambda, weighted, X, status);
-      return;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    dispatch_dual<K, N + 1, NHI>(nmax, F, n, ptr, idx, val, row, lambda, weighted, X, status);
-  } else {
-    solve16<N, K, true>(F, n, ptr, idx, val, row, lambda, weighted, X, status);
   }
+
+  // ---- right-hand side, replicated in the P lanes of the system
+  float b[D];
+  if constexpr (DUAL) {
+    sfor<0, D>([&](auto i) { b[i] = vxs[sme * E + i]; });
+  } else {
+    // b = F_O^T r, gathered from the quad layout (P = 4 here: the quad is the system)
+    static_assert(DUAL || P == 4, "primal systems use four lanes");
+    sfor<0, N>([&](auto J) {
+      sfor<0, 4>([&](auto Q) { b[4 * J + decltype(Q)::value] = quad_bcast_c<decltype(Q)::value>(pb[J]); });
+    });
+    my_flags |= pflags;
+  }
+
+  // ---- elimination with fused forward substitution
+  int bad = 0;
+  sfor<0, D>([&](auto Pp) {
+    constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
+    const float d = grp_bcast<P, pp>(st[mp][pp]);
+    bad |= !(d > 0.f);
+    const float s = __builtin_amdgcn_rcpf(d);
+    const float ty = -s * b[p];
+    if constexpr (P == 1) {
+      // the pivot column is the lane's own: update every later column
+      sfor<p + 1, D>([&](auto C) {
+        constexpr int c = decltype(C)::value;
+        const float lc = st[mp][c - mp] * (-s);  // -G[c][p] / d
+        b[c] = __builtin_fmaf(st[mp][c - mp], ty, b[c]);
+        sfor<c, D>([&](auto R) {
+          constexpr int r = decltype(R)::value;
+          st[c][r - c] = __builtin_fmaf(st[mp][r - mp], lc, st[c][r - c]);
+        });
+      });
+    } else {
+      // multipliers of the owned columns c = P m + pi (zero for c <= p)
+      float lc[M];
+      sfor<mp, M>([&](auto Mm) {
+        constexpr int m = decltype(Mm)::value;
+        float cand[P];
+        sfor<0, P>([&](auto k) {
+          constexpr int c = P * m + decltype(k)::value;
+          if constexpr (c > p)
+            cand[k] = grp_bcast<P, pp>(st[mp][c - P * mp]);
+          else
+            cand[k] = 0.f;
+        });
+        lc[m] = pick<P>(cand, pi) * (-s);
+      });
+      // rows below the pivot: one broadcast of G[r][p] each, used by every owned column
+      sfor<p + 1, D>([&](auto R) {
+        constexpr int r = decltype(R)::value;
+        const float g = grp_bcast<P, pp>(st[mp][r - P * mp]);
+        b[r] = __builtin_fmaf(g, ty, b[r]);
+        sfor<mp, (r / P + 1 < M ? r / P + 1 : M)>([&](auto Mm) {
+          constexpr int m = decltype(Mm)::value;
+          st[m][r - P * m] = __builtin_fmaf(g, lc[m], st[m][r - P * m]);
+        });
+      });
+    }
+  });
+
+  // ---- back substitution (x overwrites b); dot[m] accumulates sum_{r > c} G[r][c] x_r
+  float dot[M];
+  sfor<0, M>([&](auto m) { dot[m] = 0.f; });
+  sfor_down<0, D>([&](auto Pp) {
+    constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
+    const float d = grp_bcast<P, pp>(st[mp][pp]);
+    const float xo = (b[p] - dot[mp]) * __builtin_amdgcn_rcpf(d);
+    const float xp = grp_bcast<P, pp>(xo);
+    b[p] = xp;
+    sfor<0, mp + 1>([&](auto Mm) {
+      constexpr int m = decltype(Mm)::value;
+      dot[m] = __builtin_fmaf(st[m][p - P * m], xp, dot[m]);  // row p of owned column P m + pi
+    });
+  });
+
+  if constexpr (P == 2) my_flags |= __builtin_amdgcn_mov_dpp(my_flags, 0xb1, 0xf, 0xf, true);
+  if constexpr (P == 4) {
+    my_flags |= quad_xor1_i(my_flags);
+    my_flags |= quad_xor2_i(my_flags);
+  }
+  const bool good = my_row >= 0 && my_cnt > 0 && !bad && my_flags == 0;
+  if constexpr (DUAL) {
+    // u = F_O^T a; lane pi of the group forms outputs [pi K/P, (pi+1) K/P)
+    constexpr int KO = K / P;
+    f4 u[KO / 4];
+    sfor<0, KO / 4>([&](auto c) { u[c] = f4{0.f, 0.f, 0.f, 0.f}; });
+    sfor<0, D>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const int j = ixs[sme * E + i];
+      sfor<0, KO / 4>([&](auto c) { u[c] += b[i] * Fr.row4(j, pi * KO + 4 * c); });
+    });
+    if (my_row >= 0) {
+      float *out = X + my_row * K + pi * KO;
+      sfor<0, KO / 4>([&](auto c) { *reinterpret_cast<f4 *>(out + 4 * c) = good ? u[c] : f4{0.f, 0.f, 0.f, 0.f}; });
+    }
+  } else {
+    if (my_row >= 0) {
+      sfor<0, M>([&](auto Mm) {
+        constexpr int m = decltype(Mm)::value;
+        float cand[P];
+        sfor<0, P>([&](auto k) { cand[k] = b[P * m + decltype(k)::value]; });
+        X[my_row * K + P * m + pi] = good ? pick<P>(cand, pi) : 0.f;
+      });
+    }
+  }
+  if (status && my_row >= 0 && pi == 0)
+    status[my_row] = my_cnt == 0      ? OPEN_ROW_EMPTY
+                     : (my_flags & 2) ? OPEN_ROW_BADINDEX
+                     : (my_flags & 1) ? OPEN_ROW_NONFINITE
+                     : bad            ? OPEN_ROW_NONPOS_PIVOT
+                                      : OPEN_ROW_OK;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // the group's LDS lists are reused by the next group
 }
 
-// Persistent kernel over the rows of classes c_lo..c_hi (contiguous in the bucketed list).
-template <int K, int NLO, int NHI, bool DUAL>
-__global__ __launch_bounds__(256) void k_solve_tier(const float *__restrict__ F, int n, const int64_t *__restrict__ ptr,
-                                                    const int32_t *__restrict__ idx, const float *__restrict__ val,
-                                                    const int32_t *__restrict__ list, const int64_t *__restrict__ cls,
-                                                    int c_lo, int c_hi, float lambda, int weighted,
-                                                    float *__restrict__ X, int32_t *__restrict__ status) {
+// LDS budget of a block (bytes) and the factor matrix staged beside the per-wave buffers.
+constexpr int kLdsBytes = 160 * 1024;
+constexpr int kFactorLdsBytes = 64 * 1024;
+template <int K, int P, int D>
+__host__ __device__ constexpr int wave_bytes() { return wave_lds_floats(P, D) * 4; }
+
+// Persistent kernel over the rows of classes c_lo..c_hi (contiguous in the bucketed list),
+// all solved at padded dimension D (dual) or k (primal).
+template <int K, int P, int D, bool DUAL, bool LDSF>
+__global__ __launch_bounds__(256) void k_solve_class(const float *__restrict__ F, int n,
+                                                     const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                     const float *__restrict__ val, const int32_t *__restrict__ list,
+                                                     const int64_t *__restrict__ cls, int c_lo, int c_hi, float lambda,
+                                                     int weighted, float *__restrict__ X,
+                                                     int32_t *__restrict__ status) {
+  constexpr int SYS = 64 / P;
+  constexpr int WL = wave_lds_floats(P, D);
+  constexpr int FL = LDSF ? kFactorLdsBytes / 4 : 4;
+  __shared__ __attribute__((aligned(16))) float lds_all[4 * WL + FL];
   const int64_t start = cls[2 * c_lo];
   const int64_t count = cls[2 * c_hi] + cls[2 * c_hi + 1] - start;
-  const int lane = threadIdx.x & 63;
+  const int64_t end = start + count;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g * 16 < count; g += nw) {
-    const int64_t slot = g * 16 + (lane >> 2);
-    const int64_t row = slot < count ? (int64_t)list[start + slot] : -1;
-    if constexpr (DUAL) {
-      const int cnt = row >= 0 ? (int)(ptr[row + 1] - ptr[row]) : 0;
-      const int nmax = wave_max_i(cnt);
-      dispatch_dual<K, NLO, NHI>(nmax, F, n, ptr, idx, val, row, lambda, weighted, X, status);
-    } else {
-      solve16<K / 4, K, false>(F, n, ptr, idx, val, row, lambda, weighted, X, status);
+  const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if ((int64_t)blockIdx.x * (blockDim.x >> 6) * SYS >= count) return;  // block has no work (uniform)
+  FRows<K, LDSF> Fr;
+  if constexpr (LDSF) {
+    float *fl = lds_all + 4 * WL;
+    for (int e = threadIdx.x; e < n * (K / 4); e += blockDim.x) {
+      const int j = e / (K / 4), c = e % (K / 4);
+      *reinterpret_cast<f4 *>(fl + FRows<K, true>::slot(j, c)) =
+          *reinterpret_cast<const f4 *>(F + (int64_t)j * K + 4 * c);
     }
+    __syncthreads();
+    Fr.lds = fl;
+  } else {
+    Fr.rs = make_rsrc(F, (uint64_t)n * K * sizeof(float));
   }
+  float *wl = lds_all + (threadIdx.x >> 6) * WL;
+  for (int64_t g = g0; g * SYS < count; g += nw)
+    solve_group<P, D, K, DUAL, LDSF>(Fr, n, ptr, idx, val, list, start + g * SYS, end, lambda, weighted, X, status,
+                                     wl);
 }
 
-// Launch one tier kernel (classes c_lo..c_hi) with a persistent grid sized for m rows.
-template <int K, int NLO, int NHI, bool DUAL>
-open_status launch_tier(const char *name, open_ctx *ctx, const float *F, int n, const int64_t *ptr, const int32_t *idx, const float *val,
-                        float lambda, int weighted, const int32_t *list, const int64_t *cls, int c_lo, int c_hi,
-                        float *X, int32_t *status, int64_t m) {
-  const int64_t groups = (m + 15) / 16;
+// Launch the kernel of one size class with a persistent grid sized for m rows.
+template <int K, int P, int D, bool DUAL>
+open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n, const int64_t *ptr,
+                         const int32_t *idx, const float *val, float lambda, int weighted, const int32_t *list,
+                         const int64_t *cls, int c_lo, int c_hi, float *X, int32_t *status, int64_t m) {
+  const int64_t groups = (m + 64 / P - 1) / (64 / P);
   int64_t blocks = (groups + 3) / 4;
-  const int64_t cap = (int64_t)ctx->num_cu * 4;
+  constexpr int waves_b = 4 * wave_bytes<K, P, D>();
+  constexpr bool fl_fits = waves_b + kFactorLdsBytes <= kLdsBytes;
+  // stage the factors in LDS when they fit beside the per-wave buffers
+  const bool fl = fl_fits && (int64_t)n * K * 4 <= kFactorLdsBytes;
+  const int per_cu = kLdsBytes / (waves_b + (fl ? kFactorLdsBytes : 16));
+  const int64_t cap = (int64_t)ctx->num_cu * (per_cu < 1 ? 1 : per_cu > 2 ? 2 : per_cu);
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  OPEN_LAUNCH(ctx, name, (k_solve_tier<K, NLO, NHI, DUAL>), dim3((unsigned)blocks), dim3(256), 0, F, n, ptr, idx, val,
-              list, cls, c_lo, c_hi, lambda, weighted, X, status);
+  if constexpr (fl_fits) {
+    if (fl) {
+      OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, true>), dim3((unsigned)blocks), dim3(256), 0, F, n, ptr,
+                  idx, val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
+      return OPEN_OK;
+    }
+  }
+  OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, false>), dim3((unsigned)blocks), dim3(256), 0, F, n, ptr, idx,
+              val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
   return OPEN_OK;
 }
 
-#define OPEN_TIER_ARGS                                                                                       \
+#define OPEN_TIER_ARGS                                                                                    \
   open_ctx *ctx, const float *F, int n, const int64_t *ptr, const int32_t *idx, const float *val, float lambda, \
       int weighted, const int32_t *list, const int64_t *cls, float *X, int32_t *status, int64_t m
 #define OPEN_TIER_PASS ctx, F, n, ptr, idx, val, lambda, weighted, list, cls
-// one function per (rank, tier), each compiled in its own translation unit
-open_status tier_k8_dual(OPEN_TIER_ARGS);
-open_status tier_k8_primal(OPEN_TIER_ARGS);
-open_status tier_k16_dual(OPEN_TIER_ARGS);
-open_status tier_k16_primal(OPEN_TIER_ARGS);
-open_status tier_k32_d14(OPEN_TIER_ARGS);
-open_status tier_k32_d56(OPEN_TIER_ARGS);
-open_status tier_k32_d78(OPEN_TIER_ARGS);
-open_status tier_k32_primal(OPEN_TIER_ARGS);
-open_status tier_k64_d14(OPEN_TIER_ARGS);
-open_status tier_k64_d56(OPEN_TIER_ARGS);
-open_status tier_k64_d78(OPEN_TIER_ARGS);
+// the kernels of each rank, each rank's group compiled in its own translation unit
+open_status classes_k8(OPEN_TIER_ARGS);
+open_status classes_k16(OPEN_TIER_ARGS);
+open_status classes_k32_small(OPEN_TIER_ARGS);
+open_status classes_k32_mid(OPEN_TIER_ARGS);
+open_status classes_k32_large(OPEN_TIER_ARGS);
+open_status classes_k32_primal(OPEN_TIER_ARGS);
+open_status classes_k64_small(OPEN_TIER_ARGS);
+open_status classes_k64_mid(OPEN_TIER_ARGS);
+open_status classes_k64_large(OPEN_TIER_ARGS);
 
 }  // namespace openk

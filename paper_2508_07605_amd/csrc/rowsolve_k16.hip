@@ -1,14 +1,16 @@
-// Ridge-solve tier kernels instantiated in their own translation unit (parallel build).
+// Ridge-solve kernels of one group of size classes, in their own translation unit.
 #include "rowsolve.h"
 
 namespace openk {
 
-open_status tier_k16_dual(OPEN_TIER_ARGS) {
-  return launch_tier<16, 1, 4, true>("ridge_k16_dual", OPEN_TIER_PASS, 0, 4, X, status, m);
-}
-
-open_status tier_k16_primal(OPEN_TIER_ARGS) {
-  return launch_tier<16, 4, 4, false>("ridge_k16_primal", OPEN_TIER_PASS, 9, 15, X, status, m);
+open_status classes_k16(OPEN_TIER_ARGS) {
+  open_status st;
+  if ((st = launch_class<16, 1, 4, true>("ridge_k16_d4", OPEN_TIER_PASS, 0, 1, X, status, m))) return st;
+  if ((st = launch_class<16, 1, 8, true>("ridge_k16_d8", OPEN_TIER_PASS, 2, 2, X, status, m))) return st;
+  if ((st = launch_class<16, 1, 12, true>("ridge_k16_d12", OPEN_TIER_PASS, 3, 3, X, status, m))) return st;
+  if ((st = launch_class<16, 1, 16, true>("ridge_k16_d16", OPEN_TIER_PASS, 4, 4, X, status, m))) return st;
+  if ((st = launch_class<16, 4, 16, false>("ridge_k16_primal", OPEN_TIER_PASS, 9, 15, X, status, m))) return st;
+  return OPEN_OK;
 }
 
 }  // namespace openk
