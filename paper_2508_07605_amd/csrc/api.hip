@@ -191,7 +191,7 @@ open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int
   if (m > 0 && !U_out) return fail(ctx, OPEN_E_INVALID, "output must not be NULL");
   if (m == 0) return OPEN_OK;
   OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  int32_t *list;
+  RowRef *list;
   int64_t *cls;
   if ((st = bucket_rows(ctx, m, row_ptr, k, &list, &cls, INT64_MAX))) return st;
   if (k == 64) {

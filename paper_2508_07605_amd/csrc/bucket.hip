@@ -15,7 +15,7 @@ __global__ void k_fill_i32(int *p, int64_t n, int v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-constexpr int kRowsPerBlock = 1024;
+constexpr int kRowsPerBlock = 2048;
 constexpr int kBucketThreads = 256;
 
 __device__ __forceinline__ int row_class(int64_t cnt, int k, int64_t split_min) {
@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_count(int64_t m, const
 }
 
 // Exclusive scan of the class-major histogram (one block); cls[2c] = start, cls[2c+1] = count.
+// Each thread owns a contiguous run of up to 32 entries, loaded at once.
 __global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist, int nblk,
                                                      int64_t *__restrict__ cls) {
   __shared__ int64_t part[1024];
@@ -62,22 +63,39 @@ __global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist,
   const int per = (total + 1023) / 1024;
   const int b0 = threadIdx.x * per;
   const int b1 = b0 + per < total ? b0 + per : total;
+  constexpr int R = 32;
+  int v[R];
   int64_t s = 0;
-  for (int i = b0; i < b1; ++i) s += hist[i];
+  if (per <= R) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = b0 + u < b1 ? hist[b0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) s += v[u];
+  } else {
+    for (int i = b0; i < b1; ++i) s += hist[i];
+  }
   part[threadIdx.x] = s;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+    const int64_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
     __syncthreads();
-    part[threadIdx.x] += v;
+    part[threadIdx.x] += x;
     __syncthreads();
   }
   const int64_t total_rows = part[1023];
   int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-  for (int i = b0; i < b1; ++i) {
-    const int64_t h = hist[i];
-    hist[i] = (int32_t)run;
-    run += h;
+  if (per <= R) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (b0 + u < b1) hist[b0 + u] = (int32_t)run;
+      run += v[u];
+    }
+  } else {
+    for (int i = b0; i < b1; ++i) {
+      const int64_t h = hist[i];
+      hist[i] = (int32_t)run;
+      run += h;
+    }
   }
   __syncthreads();
   if (threadIdx.x < kNumClasses) {
@@ -92,7 +110,7 @@ __global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist,
 __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const int64_t *__restrict__ ptr,
                                                                 const uint8_t *__restrict__ mask, int k,
                                                                 int64_t split_min, const int32_t *__restrict__ offs,
-                                                                int32_t *__restrict__ list) {
+                                                                RowRef *__restrict__ list) {
   __shared__ int wcnt[kBucketThreads / kWave][kNumClasses];
   __shared__ int run[kNumClasses];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -111,7 +129,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
     if (c >= 0) {
       int pos = run[c];
       for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][c];
-      list[pos + rank] = (int32_t)i;
+      const int64_t beg = ptr[i];
+      list[pos + rank] = RowRef{(int32_t)i, (int32_t)(ptr[i + 1] - beg), beg};
     }
     __syncthreads();
     if (tid < kNumClasses) {
@@ -123,14 +142,14 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
   }
 }
 
-open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t **list, int64_t **cls,
+open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, RowRef **list, int64_t **cls,
                         int64_t split_min, const uint8_t *mask) {
   const int nblk = (int)((m + kRowsPerBlock - 1) / kRowsPerBlock);
   void *hist = nullptr, *lst = nullptr, *c = nullptr;
   open_status st;
   if ((st = ws_get(ctx, open_ctx::WS_HIST, sizeof(int32_t) * (size_t)kNumClasses * (nblk > 0 ? nblk : 1), &hist)))
     return st;
-  if ((st = ws_get(ctx, open_ctx::WS_LIST, sizeof(int32_t) * (size_t)(m > 0 ? m : 1), &lst))) return st;
+  if ((st = ws_get(ctx, open_ctx::WS_LIST, sizeof(RowRef) * (size_t)(m > 0 ? m : 1), &lst))) return st;
   if ((st = ws_get(ctx, open_ctx::WS_CLS, sizeof(int64_t) * 2 * kNumClasses, &c))) return st;
   if (m > 0) {
     OPEN_LAUNCH(ctx, "bucket_count", k_class_count, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask, k,
@@ -139,9 +158,9 @@ open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k,
   OPEN_LAUNCH(ctx, "bucket_scan", k_class_scan, dim3(1), dim3(1024), 0, (int32_t *)hist, nblk, (int64_t *)c);
   if (m > 0) {
     OPEN_LAUNCH(ctx, "bucket_place", k_class_place, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask, k,
-                split_min, (const int32_t *)hist, (int32_t *)lst);
+                split_min, (const int32_t *)hist, (RowRef *)lst);
   }
-  *list = (int32_t *)lst;
+  *list = (RowRef *)lst;
   *cls = (int64_t *)c;
   return OPEN_OK;
 }

@@ -165,22 +165,29 @@ void prof_end(open_ctx *ctx);
 open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out);
 open_status pinned_get(open_ctx *ctx, size_t bytes, void **out);
 
+// Entry of the bucketed row list: the row and its observed range, so a solver reads one
+// 16-byte record instead of the list and then the row pointer.
+struct RowRef {
+  int32_t row, cnt;
+  int64_t beg;
+};
+
 // ---- internal launchers (defined in the .hip files)
 // Row classification + stable counting sort; fills list[m] (row ids grouped by class) and
 // cls[2*kNumClasses] = {start, count} per class, on the device.
 constexpr int kNumClasses = 17;
 constexpr int kSplitClass = 16;  // rows solved by the split-K column path
-open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t **list, int64_t **cls,
+open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, RowRef **list, int64_t **cls,
                         int64_t split_min, const uint8_t *mask = nullptr);
 // Column view on the device (stable counting sort); entries with a column outside [0, n) are dropped.
 open_status csr_to_csc_dev(open_ctx *ctx, int64_t m, int n, const int64_t *row_ptr, const int32_t *col,
                            const float *val, int64_t *col_ptr, int32_t *row_idx, float *cval);
 // Ridge solve of all rows given a bucketing.
 open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const int64_t *row_ptr, const int32_t *col,
-                            const float *val, float lambda, int weighted, const int32_t *list, const int64_t *cls,
+                            const float *val, float lambda, int weighted, const RowRef *list, const int64_t *cls,
                             float *X, int32_t *status, int64_t m);
 open_status splitk_launch(open_ctx *ctx, const float *F, int k, const int64_t *row_ptr, const int32_t *col,
-                          const float *val, float lambda, int weighted, const int32_t *list, const int64_t *cls,
+                          const float *val, float lambda, int weighted, const RowRef *list, const int64_t *cls,
                           float *X, int32_t *status, int64_t m);
 
 }  // namespace openk

@@ -387,27 +387,28 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
   OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   // caller-independent buffers of this call: the column view and the two bucketings
   int64_t *cp = nullptr;
-  int32_t *ri = nullptr, *list_r = nullptr, *list_c = nullptr;
+  int32_t *ri = nullptr;
+  RowRef *list_r = nullptr, *list_c = nullptr;
   float *cv = nullptr;
   int64_t *cls_r = nullptr, *cls_c = nullptr;
   double *obj_d = nullptr;
   open_status st = OPEN_OK;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(ctx->stream);
-    hipFree(cp);
-    hipFree(ri);
-    hipFree(cv);
-    hipFree(list_r);
-    hipFree(list_c);
-    hipFree(cls_r);
-    hipFree(cls_c);
-    hipFree(obj_d);
+    (void)hipFree(cp);
+    (void)hipFree(ri);
+    (void)hipFree(cv);
+    (void)hipFree(list_r);
+    (void)hipFree(list_c);
+    (void)hipFree(cls_r);
+    (void)hipFree(cls_c);
+    (void)hipFree(obj_d);
   };
   if (hipMalloc(&cp, sizeof(int64_t) * (n + 1)) != hipSuccess ||
       hipMalloc(&ri, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)) != hipSuccess ||
       hipMalloc(&cv, sizeof(float) * (size_t)(nnz > 0 ? nnz : 1)) != hipSuccess ||
-      hipMalloc(&list_r, sizeof(int32_t) * (size_t)m) != hipSuccess ||
-      hipMalloc(&list_c, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+      hipMalloc(&list_r, sizeof(RowRef) * (size_t)m) != hipSuccess ||
+      hipMalloc(&list_c, sizeof(RowRef) * (size_t)n) != hipSuccess ||
       hipMalloc(&cls_r, sizeof(int64_t) * 2 * kNumClasses) != hipSuccess ||
       hipMalloc(&cls_c, sizeof(int64_t) * 2 * kNumClasses) != hipSuccess ||
       hipMalloc(&obj_d, sizeof(double) * 2 * (sweeps > 0 ? sweeps : 1)) != hipSuccess) {
@@ -418,17 +419,17 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
   do {
     if ((st = check_cols(ctx, nnz, col, n))) break;
     if ((st = csr_to_csc_dev(ctx, m, n, row_ptr, col, val, cp, ri, cv))) break;
-    int32_t *l;
+    RowRef *l;
     int64_t *c;
     if ((st = bucket_rows(ctx, m, row_ptr, k, &l, &c, INT64_MAX))) break;
-    if (hipMemcpyAsync(list_r, l, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+    if (hipMemcpyAsync(list_r, l, sizeof(RowRef) * m, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
         hipMemcpyAsync(cls_r, c, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToDevice, ctx->stream) !=
             hipSuccess) {
       st = fail(ctx, OPEN_E_DEVICE, "copy");
       break;
     }
     if ((st = bucket_rows(ctx, n, cp, k, &l, &c, INT64_MAX))) break;
-    if (hipMemcpyAsync(list_c, l, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+    if (hipMemcpyAsync(list_c, l, sizeof(RowRef) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
         hipMemcpyAsync(cls_c, c, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToDevice, ctx->stream) !=
             hipSuccess) {
       st = fail(ctx, OPEN_E_DEVICE, "copy");

@@ -666,7 +666,7 @@ open_status open_mlp_foldin(open_mlp *p, const float *F, int64_t m, const int64_
   if ((st = open_residual(ctx, m, p->n, p->k, row_ptr, col, val, U_out, F, r))) return st;
   OPEN_LAUNCH(ctx, "mlp_fallback_flag", k_fallback_flag, dim3(1024), dim3(256), 0, m, row_ptr, r, tau, f);
   // re-solve the flagged rows with the ridge fold-in (only they are bucketed)
-  int32_t *list;
+  RowRef *list;
   int64_t *cls;
   if ((st = bucket_rows(ctx, m, row_ptr, p->k, &list, &cls, INT64_MAX, f))) return st;
   if ((st = rowsolve_launch(ctx, F, p->n, p->k, row_ptr, col, val, lambda, weighted, list, cls, U_out, nullptr, m)))

@@ -92,9 +92,8 @@ __host__ __device__ constexpr int wave_lds_floats(int P, int D) {
 }
 
 template <int P, int D, int K, bool DUAL, bool LDSF>
-__device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, const int64_t *__restrict__ ptr,
+__device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, const RowRef mine,
                                             const int32_t *__restrict__ idx, const float *__restrict__ val,
-                                            const int32_t *__restrict__ list, int64_t slot0, int64_t end,
                                             float lambda, int weighted, float *__restrict__ X,
                                             int32_t *__restrict__ status, float *__restrict__ wl) {
   constexpr int N = D / 4;            // tiles per dimension
@@ -114,12 +113,11 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
   int *ixs = reinterpret_cast<int *>(wl + (P < 4 ? 16 * ST : 0));  // [SYS][E] column indices (-1 = none)
   float *vxs = wl + (P < 4 ? 16 * ST : 0) + SYS * E;               // [SYS][E] values
 
-  // ---- this lane's system: row, count, flags; its index/value lists into LDS
-  const int64_t myslot = slot0 + sme;
-  const int64_t my_row = myslot < end ? (int64_t)list[myslot] : -1;
-  const int64_t mrr = my_row >= 0 ? my_row : 0;
-  const int64_t mbeg = ptr[mrr];
-  const int my_cnt = my_row >= 0 ? (int)(ptr[mrr + 1] - mbeg) : 0;
+  // ---- this lane's system (record prefetched by the caller): row, range, flags; its
+  // index/value lists into LDS
+  const int64_t my_row = mine.row;
+  const int64_t mbeg = mine.beg;
+  const int my_cnt = mine.cnt;
   int my_flags = 0;  // 1: non-finite value, 2: column index out of range
   if constexpr (DUAL) {
     // lane pi of the group fetches entries pi, pi + P, ...
@@ -166,10 +164,12 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
     if constexpr (DUAL) {
       int oi[N];
       sfor<0, N>([&](auto J) { oi[J] = ixs[qs * E + 4 * J + qi]; });
+      f4 a[N];
+      sfor<0, N>([&](auto J) { a[J] = Fr.row4(oi[J], 0); });
       sfor<0, K / 4>([&](auto C) {
         constexpr int k0 = 4 * C;
-        f4 a[N];
-        sfor<0, N>([&](auto J) { a[J] = Fr.row4(oi[J], k0); });
+        f4 an[N];  // next chunk, read while this one feeds the MFMAs
+        if constexpr (k0 + 4 < K) sfor<0, N>([&](auto J) { an[J] = Fr.row4(oi[J], k0 + 4); });
         sfor<0, 4>([&](auto kk) {
           sfor<0, N>([&](auto I) {
             sfor<0, I + 1>([&](auto J) {
@@ -177,12 +177,12 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
             });
           });
         });
+        if constexpr (k0 + 4 < K) sfor<0, N>([&](auto J) { a[J] = an[J]; });
       });
     } else {
       // primal: contraction over the observations of the 16 systems, in step
-      const int64_t qrow = __shfl((int)(my_row & 0xffffffff), qsrc, 64) |
-                           ((int64_t)__shfl((int)(my_row >> 32), qsrc, 64) << 32);
-      const int64_t qbeg = qrow >= 0 ? ptr[qrow] : 0;
+      const int64_t qbeg = (int64_t)(uint32_t)__shfl((int)(mbeg & 0xffffffff), qsrc, 64) |
+                           ((int64_t)__shfl((int)(mbeg >> 32), qsrc, 64) << 32);
       const int tmax = wave_max_i(cnt);
       int jn = 0;
       float rn = 0.f;
@@ -385,13 +385,13 @@ __host__ __device__ constexpr int wave_bytes() { return wave_lds_floats(P, D) * 
 template <int K, int P, int D, bool DUAL, bool LDSF>
 __global__ __launch_bounds__(256) void k_solve_class(const float *__restrict__ F, int n,
                                                      const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                     const float *__restrict__ val, const int32_t *__restrict__ list,
+                                                     const float *__restrict__ val, const RowRef *__restrict__ list,
                                                      const int64_t *__restrict__ cls, int c_lo, int c_hi, float lambda,
                                                      int weighted, float *__restrict__ X,
                                                      int32_t *__restrict__ status) {
   constexpr int SYS = 64 / P;
   constexpr int WL = wave_lds_floats(P, D);
-  constexpr int FL = LDSF ? kFactorLdsBytes / 4 : 4;
+  constexpr int FL = LDSF ? kFactorLdsBytes / 4 + 256 : 4;  // + one wave instruction of tail
   __shared__ __attribute__((aligned(16))) float lds_all[4 * WL + FL];
   const int64_t start = cls[2 * c_lo];
   const int64_t count = cls[2 * c_hi] + cls[2 * c_hi + 1] - start;
@@ -402,31 +402,47 @@ __global__ __launch_bounds__(256) void k_solve_class(const float *__restrict__ F
   FRows<K, LDSF> Fr;
   if constexpr (LDSF) {
     float *fl = lds_all + 4 * WL;
-    for (int e = threadIdx.x; e < n * (K / 4); e += blockDim.x) {
-      const int j = e / (K / 4), c = e % (K / 4);
-      *reinterpret_cast<f4 *>(fl + FRows<K, true>::slot(j, c)) =
-          *reinterpret_cast<const f4 *>(F + (int64_t)j * K + 4 * c);
+    // direct global -> LDS copies: one 16-byte chunk per lane, 1 KB per wave instruction;
+    // LDS chunk (j, c) holds global chunk c ^ (j mod K/4) (the swizzle is an involution)
+    constexpr int CH = K / 4;
+    const int chunks = n * CH;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int base = w * 64; base < chunks; base += 4 * 64) {
+      const int e = base + lane;
+      const int ee = e < chunks ? e : chunks - 1;  // tail lanes copy a valid chunk past the end
+      const int jj = ee / CH, cc = ee % CH;
+      __builtin_amdgcn_global_load_lds(F + (int64_t)jj * K + 4 * (cc ^ (jj & (CH - 1))),
+                                       (__attribute__((address_space(3))) void *)(fl + 4 * base), 16, 0, 0);
     }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     Fr.lds = fl;
   } else {
     Fr.rs = make_rsrc(F, (uint64_t)n * K * sizeof(float));
   }
   float *wl = lds_all + (threadIdx.x >> 6) * WL;
-  for (int64_t g = g0; g * SYS < count; g += nw)
-    solve_group<P, D, K, DUAL, LDSF>(Fr, n, ptr, idx, val, list, start + g * SYS, end, lambda, weighted, X, status,
-                                     wl);
+  const int sme = (threadIdx.x & 63) / P;
+  auto fetch = [&](int64_t g) -> RowRef {
+    const int64_t sl = start + g * SYS + sme;
+    return (g * SYS < count && sl < end) ? list[sl] : RowRef{-1, 0, 0};
+  };
+  RowRef cur = fetch(g0);
+  for (int64_t g = g0; g * SYS < count; g += nw) {
+    const RowRef nxt = fetch(g + nw);  // next group's records load while this group computes
+    solve_group<P, D, K, DUAL, LDSF>(Fr, n, cur, idx, val, lambda, weighted, X, status, wl);
+    cur = nxt;
+  }
 }
 
 // Launch the kernel of one size class with a persistent grid sized for m rows.
 template <int K, int P, int D, bool DUAL>
 open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n, const int64_t *ptr,
-                         const int32_t *idx, const float *val, float lambda, int weighted, const int32_t *list,
+                         const int32_t *idx, const float *val, float lambda, int weighted, const RowRef *list,
                          const int64_t *cls, int c_lo, int c_hi, float *X, int32_t *status, int64_t m) {
   const int64_t groups = (m + 64 / P - 1) / (64 / P);
   int64_t blocks = (groups + 3) / 4;
   constexpr int waves_b = 4 * wave_bytes<K, P, D>();
-  constexpr bool fl_fits = waves_b + kFactorLdsBytes <= kLdsBytes;
+  constexpr bool fl_fits = waves_b + kFactorLdsBytes + 1024 <= kLdsBytes;
   // stage the factors in LDS when they fit beside the per-wave buffers
   const bool fl = fl_fits && (int64_t)n * K * 4 <= kFactorLdsBytes;
   const int per_cu = kLdsBytes / (waves_b + (fl ? kFactorLdsBytes : 16));
@@ -447,7 +463,7 @@ open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n,
 
 #define OPEN_TIER_ARGS                                                                                    \
   open_ctx *ctx, const float *F, int n, const int64_t *ptr, const int32_t *idx, const float *val, float lambda, \
-      int weighted, const int32_t *list, const int64_t *cls, float *X, int32_t *status, int64_t m
+      int weighted, const RowRef *list, const int64_t *cls, float *X, int32_t *status, int64_t m
 #define OPEN_TIER_PASS ctx, F, n, ptr, idx, val, lambda, weighted, list, cls
 // the kernels of each rank, each rank's group compiled in its own translation unit
 open_status classes_k8(OPEN_TIER_ARGS);

@@ -4,7 +4,7 @@
 namespace openk {
 
 open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const int64_t *ptr, const int32_t *idx,
-                            const float *val, float lambda, int weighted, const int32_t *list, const int64_t *cls,
+                            const float *val, float lambda, int weighted, const RowRef *list, const int64_t *cls,
                             float *X, int32_t *status, int64_t m) {
   open_status st = OPEN_OK;
   switch (k) {
