@@ -95,6 +95,32 @@ open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int
                         int32_t *row_status);
 
 /*
+ * Kernel variants and autotuning (the fold-in's batched solves, Section III-B.2, run one
+ * kernel per size class of |O_i|; each class group has up to 4 compiled configurations:
+ * lanes per system, waves per block, waves per SIMD).  The choice is per context and rank
+ * and applies to every later call that solves ridge rows (open_foldin, open_fit, the
+ * surrogate fallback).
+ *
+ * open_tune_info: number of class groups of rank k (8, 16, 32, 64; -1 otherwise); for the
+ *   first `max` groups, names[g] (static strings) and nvar[g] (variants compiled), either
+ *   array may be NULL.
+ * open_tune_get / open_tune_set: the chosen variant per group, host int8[count]; set
+ *   rejects a value outside [0, nvar) with OPEN_E_INVALID and changes nothing then.
+ * open_autotune: the arguments of open_foldin plus `reps` (>= 1 timed launches per
+ *   variant after one untimed one).  Buckets the batch once, times every variant of each
+ *   group that holds rows, keeps the fastest, and leaves the fold-in result of the chosen
+ *   variants in U_out (and row_status).  Groups without rows keep their choice.  ms_out
+ *   (host float64[groups * 4] or NULL) receives milliseconds per launch, -1 where untimed.
+ *   Synchronises the stream.
+ */
+int32_t open_tune_info(int32_t k, const char **names, int32_t *nvar, int32_t max);
+open_status open_tune_get(open_ctx *ctx, int32_t k, int8_t *choice, int32_t count);
+open_status open_tune_set(open_ctx *ctx, int32_t k, const int8_t *choice, int32_t count);
+open_status open_autotune(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m, const int64_t *row_ptr,
+                          const int32_t *col, const float *val, float lambda, int32_t weighted, float *U_out,
+                          int32_t *row_status, int32_t reps, double *ms_out);
+
+/*
  * Column view of a CSR matrix (m x n): col_ptr int64[n+1], row_idx int32[nnz] and
  * cval float32[nnz], entries ordered by column and, within a column, by row.  Exact
  * integer work (a stable counting sort).  All pointers are device pointers.

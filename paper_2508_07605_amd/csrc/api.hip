@@ -9,6 +9,7 @@
 #include <string>
 
 #include "common.h"
+#include "rowsolve.h"
 
 namespace openk {
 
@@ -179,10 +180,10 @@ open_status open_sync(open_ctx *ctx) {
   return OPEN_OK;
 }
 
-open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m, const int64_t *row_ptr,
-                        const int32_t *col, const float *val, float lambda, int32_t weighted, float *U_out,
-                        int32_t *row_status) {
-  if (!ctx) return OPEN_E_INVALID;
+// Shared front half of open_foldin and open_autotune: validation and bucketing.
+static open_status foldin_prepare(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m,
+                                  const int64_t *row_ptr, const int32_t *col, const float *val, float lambda,
+                                  float *U_out, RowRef **list, int64_t **cls) {
   if (!rank_ok(k)) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
   if (n <= 0 || !F) return fail(ctx, OPEN_E_INVALID, "factor matrix must be non-empty");
   if (!(lambda >= 0.0f) || !isfinite(lambda)) return fail(ctx, OPEN_E_INVALID, "lambda must be finite and >= 0");
@@ -191,20 +192,74 @@ open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int
   if (m > 0 && !U_out) return fail(ctx, OPEN_E_INVALID, "output must not be NULL");
   if (m == 0) return OPEN_OK;
   OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  RowRef *list;
-  int64_t *cls;
-  if ((st = bucket_rows(ctx, m, row_ptr, k, &list, &cls, INT64_MAX))) return st;
+  if ((st = bucket_rows(ctx, m, row_ptr, k, list, cls, INT64_MAX))) return st;
   if (k == 64) {
     // rank 64 solves only the dual form (n_i <= 32) in this build
     int64_t *h;
     if ((st = pinned_get(ctx, sizeof(int64_t) * 2 * kNumClasses, (void **)&h))) return st;
-    OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, cls, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToHost, ctx->stream));
+    OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, *cls, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToHost, ctx->stream));
     OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     int64_t big = 0;
     for (int c = 9; c < kNumClasses; ++c) big += h[2 * c + 1];
     if (big) return fail(ctx, OPEN_E_UNSUPPORTED, "rank 64 with more than 32 observed entries in a row");
   }
+  return OPEN_OK;
+}
+
+open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m, const int64_t *row_ptr,
+                        const int32_t *col, const float *val, float lambda, int32_t weighted, float *U_out,
+                        int32_t *row_status) {
+  if (!ctx) return OPEN_E_INVALID;
+  RowRef *list = nullptr;
+  int64_t *cls = nullptr;
+  open_status st = foldin_prepare(ctx, F, n, k, m, row_ptr, col, val, lambda, U_out, &list, &cls);
+  if (st || m == 0) return st;
   return rowsolve_launch(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m);
+}
+
+int32_t open_tune_info(int32_t k, const char **names, int32_t *nvar, int32_t max) {
+  int ng = 0;
+  const ClassGroup *g = class_groups(k, &ng);
+  if (!g) return -1;
+  for (int i = 0; i < ng && i < max; ++i) {
+    if (names) names[i] = g[i].name;
+    if (nvar) nvar[i] = g[i].nvar;
+  }
+  return ng;
+}
+
+open_status open_tune_get(open_ctx *ctx, int32_t k, int8_t *choice, int32_t count) {
+  if (!ctx) return OPEN_E_INVALID;
+  int ng = 0;
+  if (!class_groups(k, &ng)) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
+  if (count != ng || !choice) return fail(ctx, OPEN_E_INVALID, "choice array must hold one entry per class group");
+  memcpy(choice, ctx->tune[rank_index(k)], (size_t)ng);
+  return OPEN_OK;
+}
+
+open_status open_tune_set(open_ctx *ctx, int32_t k, const int8_t *choice, int32_t count) {
+  if (!ctx) return OPEN_E_INVALID;
+  int ng = 0;
+  const ClassGroup *g = class_groups(k, &ng);
+  if (!g) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
+  if (count != ng || !choice) return fail(ctx, OPEN_E_INVALID, "choice array must hold one entry per class group");
+  for (int i = 0; i < ng; ++i)
+    if (choice[i] < 0 || choice[i] >= g[i].nvar) return fail(ctx, OPEN_E_INVALID, "variant out of range");
+  memcpy(ctx->tune[rank_index(k)], choice, (size_t)ng);
+  return OPEN_OK;
+}
+
+open_status open_autotune(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m, const int64_t *row_ptr,
+                          const int32_t *col, const float *val, float lambda, int32_t weighted, float *U_out,
+                          int32_t *row_status, int32_t reps, double *ms_out) {
+  if (!ctx) return OPEN_E_INVALID;
+  if (reps < 1) return fail(ctx, OPEN_E_INVALID, "reps must be >= 1");
+  RowRef *list = nullptr;
+  int64_t *cls = nullptr;
+  open_status st = foldin_prepare(ctx, F, n, k, m, row_ptr, col, val, lambda, U_out, &list, &cls);
+  if (st || m == 0) return st;
+  return rowsolve_autotune(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m, reps,
+                           ms_out);
 }
 
 }  // extern "C"

@@ -115,6 +115,8 @@ struct open_ctx {
   };
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};
+  // chosen kernel variant of each size-class group, per rank (8, 16, 32, 64); 0 = default
+  int8_t tune[4][16] = {};
   void *host_pinned = nullptr;  // small pinned staging buffer for synchronous scalar results
   size_t host_pinned_bytes = 0;
   // optional per-kernel timing (HIP events around each launch)
@@ -186,8 +188,13 @@ open_status csr_to_csc_dev(open_ctx *ctx, int64_t m, int n, const int64_t *row_p
 open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const int64_t *row_ptr, const int32_t *col,
                             const float *val, float lambda, int weighted, const RowRef *list, const int64_t *cls,
                             float *X, int32_t *status, int64_t m);
-open_status splitk_launch(open_ctx *ctx, const float *F, int k, const int64_t *row_ptr, const int32_t *col,
-                          const float *val, float lambda, int weighted, const RowRef *list, const int64_t *cls,
-                          float *X, int32_t *status, int64_t m);
+// Kernel variants: at most kMaxVariants per class group; rank_index maps 8/16/32/64 to 0..3.
+constexpr int kMaxVariants = 4;
+int rank_index(int k);
+// Time the variants of each populated class group on this batch and keep the fastest;
+// ms_out (host, optional) receives [group][kMaxVariants] milliseconds per launch, -1 if untimed.
+open_status rowsolve_autotune(open_ctx *ctx, const float *F, int n, int k, const int64_t *row_ptr,
+                              const int32_t *col, const float *val, float lambda, int weighted, const RowRef *list,
+                              const int64_t *cls, float *X, int32_t *status, int64_t m, int reps, double *ms_out);
 
 }  // namespace openk

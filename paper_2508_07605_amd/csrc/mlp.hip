@@ -352,11 +352,11 @@ constexpr int kLossBlocks = 256;
 
 static void mlp_free_batch(open_mlp *p) {
   float *fs[] = {p->z1, p->h1, p->z2, p->h2, p->out, p->dout, p->d2, p->d1, p->bval, p->crv};
-  for (float *f : fs) hipFree(f);
-  hipFree(p->bptr);
-  hipFree(p->bcol);
-  hipFree(p->ccp);
-  hipFree(p->crb);
+  for (float *f : fs) (void)hipFree(f);
+  (void)hipFree(p->bptr);
+  (void)hipFree(p->bcol);
+  (void)hipFree(p->ccp);
+  (void)hipFree(p->crb);
   p->z1 = p->h1 = p->z2 = p->h2 = p->out = p->dout = p->d2 = p->d1 = p->bval = p->crv = nullptr;
   p->bptr = p->ccp = nullptr;
   p->bcol = p->crb = nullptr;
@@ -391,10 +391,10 @@ static open_status mlp_batch_buffers(open_mlp *p, int64_t B, int64_t bnnz) {
   }
   if (bnnz > p->bnnz_cap) {
     OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    hipFree(p->bcol);
-    hipFree(p->bval);
-    hipFree(p->crb);
-    hipFree(p->crv);
+    (void)hipFree(p->bcol);
+    (void)hipFree(p->bval);
+    (void)hipFree(p->crb);
+    (void)hipFree(p->crv);
     p->bcol = p->crb = nullptr;
     p->bval = p->crv = nullptr;
     const int64_t want = bnnz + bnnz / 4 + 64;
@@ -536,16 +536,16 @@ open_status open_mlp_destroy(open_mlp *p) {
   if (!p) return OPEN_E_INVALID;
   if (p->ctx) (void)hipStreamSynchronize(p->ctx->stream);
   mlp_free_batch(p);
-  hipFree(p->w);
-  hipFree(p->g);
-  hipFree(p->am);
-  hipFree(p->av);
-  hipFree(p->w1t);
-  hipFree(p->part);
-  hipFree(p->loss);
-  hipFree(p->rho);
-  hipFree(p->flag);
-  hipFree(p->cnt);
+  (void)hipFree(p->w);
+  (void)hipFree(p->g);
+  (void)hipFree(p->am);
+  (void)hipFree(p->av);
+  (void)hipFree(p->w1t);
+  (void)hipFree(p->part);
+  (void)hipFree(p->loss);
+  (void)hipFree(p->rho);
+  (void)hipFree(p->flag);
+  (void)hipFree(p->cnt);
   delete p;
   return OPEN_OK;
 }
@@ -647,9 +647,9 @@ open_status open_mlp_foldin(open_mlp *p, const float *F, int64_t m, const int64_
   open_status st;
   if (m > p->icap) {
     OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    hipFree(p->rho);
-    hipFree(p->flag);
-    hipFree(p->cnt);
+    (void)hipFree(p->rho);
+    (void)hipFree(p->flag);
+    (void)hipFree(p->cnt);
     p->rho = nullptr;
     p->flag = nullptr;
     p->cnt = nullptr;

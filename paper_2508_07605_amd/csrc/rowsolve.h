@@ -46,12 +46,15 @@ __device__ __forceinline__ float grp_bcast(float x) {
   }
 }
 
-// v[pi] for the lane's position pi in its group (compile-time array, runtime pi)
+// v[pi] for the lane's position pi in its group (compile-time array, runtime pi), as
+// selects on the bits of pi (a compare chain would become a branchy switch)
 template <int P>
 __device__ __forceinline__ float pick(const float *v, int pi) {
   if constexpr (P == 1) return v[0];
-  if constexpr (P == 2) return pi ? v[1] : v[0];
-  return pi == 0 ? v[0] : pi == 1 ? v[1] : pi == 2 ? v[2] : v[3];
+  const bool b0 = pi & 1;
+  if constexpr (P == 2) return b0 ? v[1] : v[0];
+  const float lo = b0 ? v[1] : v[0], hi = b0 ? v[3] : v[2];
+  return (pi & 2) ? hi : lo;
 }
 
 // ---------------------------------------------------------------- factor-row access
@@ -91,7 +94,7 @@ __host__ __device__ constexpr int wave_lds_floats(int P, int D) {
   return (P < 4 ? 16 * tri_stride(D) : 0) + 2 * (64 / P) * (D + 1);
 }
 
-template <int P, int D, int K, bool DUAL, bool LDSF>
+template <int P, int D, int K, bool DUAL, bool LDSF, bool PF>
 __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, const RowRef mine,
                                             const int32_t *__restrict__ idx, const float *__restrict__ val,
                                             float lambda, int weighted, float *__restrict__ X,
@@ -168,8 +171,8 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
       sfor<0, N>([&](auto J) { a[J] = Fr.row4(oi[J], 0); });
       sfor<0, K / 4>([&](auto C) {
         constexpr int k0 = 4 * C;
-        f4 an[N];  // next chunk, read while this one feeds the MFMAs
-        if constexpr (k0 + 4 < K) sfor<0, N>([&](auto J) { an[J] = Fr.row4(oi[J], k0 + 4); });
+        f4 an[N];  // with PF, the next chunk is read while this one feeds the MFMAs
+        if constexpr (PF && k0 + 4 < K) sfor<0, N>([&](auto J) { an[J] = Fr.row4(oi[J], k0 + 4); });
         sfor<0, 4>([&](auto kk) {
           sfor<0, N>([&](auto I) {
             sfor<0, I + 1>([&](auto J) {
@@ -177,7 +180,12 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
             });
           });
         });
-        if constexpr (k0 + 4 < K) sfor<0, N>([&](auto J) { a[J] = an[J]; });
+        if constexpr (k0 + 4 < K) {
+          if constexpr (PF)
+            sfor<0, N>([&](auto J) { a[J] = an[J]; });
+          else
+            sfor<0, N>([&](auto J) { a[J] = Fr.row4(oi[J], k0 + 4); });
+        }
       });
     } else {
       // primal: contraction over the observations of the 16 systems, in step
@@ -259,16 +267,14 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
     }
   }
 
-  // ---- right-hand side, replicated in the P lanes of the system
-  float b[D];
+  // ---- right-hand side, owned like the columns: lane pi holds bm[m] = b[P m + pi]
+  float bm[M];
   if constexpr (DUAL) {
-    sfor<0, D>([&](auto i) { b[i] = vxs[sme * E + i]; });
+    sfor<0, M>([&](auto m) { bm[m] = vxs[sme * E + P * m + pi]; });
   } else {
-    // b = F_O^T r, gathered from the quad layout (P = 4 here: the quad is the system)
+    // b = F_O^T r in the quad layout: lane q of the quad holds b[4J + q], the owned layout
     static_assert(DUAL || P == 4, "primal systems use four lanes");
-    sfor<0, N>([&](auto J) {
-      sfor<0, 4>([&](auto Q) { b[4 * J + decltype(Q)::value] = quad_bcast_c<decltype(Q)::value>(pb[J]); });
-    });
+    sfor<0, M>([&](auto m) { bm[m] = pb[m]; });
     my_flags |= pflags;
   }
 
@@ -279,20 +285,26 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
     const float d = grp_bcast<P, pp>(st[mp][pp]);
     bad |= !(d > 0.f);
     const float s = __builtin_amdgcn_rcpf(d);
-    const float ty = -s * b[p];
+    const float ty = -s * grp_bcast<P, pp>(bm[mp]);  // -b[p] / d
     if constexpr (P == 1) {
       // the pivot column is the lane's own: update every later column
       sfor<p + 1, D>([&](auto C) {
         constexpr int c = decltype(C)::value;
         const float lc = st[mp][c - mp] * (-s);  // -G[c][p] / d
-        b[c] = __builtin_fmaf(st[mp][c - mp], ty, b[c]);
+        bm[c] = __builtin_fmaf(st[mp][c - mp], ty, bm[c]);
         sfor<c, D>([&](auto R) {
           constexpr int r = decltype(R)::value;
           st[c][r - c] = __builtin_fmaf(st[mp][r - mp], lc, st[c][r - c]);
         });
       });
     } else {
-      // multipliers of the owned columns c = P m + pi (zero for c <= p)
+      // column p below the pivot, broadcast from its owner lane: g[r] = G[r][p]
+      float g[D];
+      sfor<p + 1, D>([&](auto R) {
+        constexpr int r = decltype(R)::value;
+        g[r] = grp_bcast<P, pp>(st[mp][r - P * mp]);
+      });
+      // owned columns c = P m + pi: multiplier -G[c][p] / d and rhs, no-ops for c <= p
       float lc[M];
       sfor<mp, M>([&](auto Mm) {
         constexpr int m = decltype(Mm)::value;
@@ -300,38 +312,51 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
         sfor<0, P>([&](auto k) {
           constexpr int c = P * m + decltype(k)::value;
           if constexpr (c > p)
-            cand[k] = grp_bcast<P, pp>(st[mp][c - P * mp]);
+            cand[k] = g[c];
           else
             cand[k] = 0.f;
         });
-        lc[m] = pick<P>(cand, pi) * (-s);
+        const float go = pick<P>(cand, pi);
+        lc[m] = go * (-s);
+        bm[m] = __builtin_fmaf(go, ty, bm[m]);
       });
-      // rows below the pivot: one broadcast of G[r][p] each, used by every owned column
       sfor<p + 1, D>([&](auto R) {
         constexpr int r = decltype(R)::value;
-        const float g = grp_bcast<P, pp>(st[mp][r - P * mp]);
-        b[r] = __builtin_fmaf(g, ty, b[r]);
         sfor<mp, (r / P + 1 < M ? r / P + 1 : M)>([&](auto Mm) {
           constexpr int m = decltype(Mm)::value;
-          st[m][r - P * m] = __builtin_fmaf(g, lc[m], st[m][r - P * m]);
+          st[m][r - P * m] = __builtin_fmaf(g[r], lc[m], st[m][r - P * m]);
         });
       });
     }
   });
 
-  // ---- back substitution (x overwrites b); dot[m] accumulates sum_{r > c} G[r][c] x_r
+  // ---- back substitution; dot[m] accumulates sum_{r > c} G[r][c] x_r for owned column c.
+  // Dual systems fold each x_p into u = F_O^T x as soon as it is known: lane pi forms the
+  // outputs [pi K/P, (pi+1) K/P).  Primal systems keep x in the owned layout.
+  constexpr int KO = K / P;
+  static_assert(!DUAL || KO % 4 == 0, "dual outputs are formed in 4-float chunks per lane");
+  f4 u[DUAL ? KO / 4 : 1];
+  if constexpr (DUAL) sfor<0, KO / 4>([&](auto c) { u[c] = f4{0.f, 0.f, 0.f, 0.f}; });
   float dot[M];
   sfor<0, M>([&](auto m) { dot[m] = 0.f; });
   sfor_down<0, D>([&](auto Pp) {
     constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
     const float d = grp_bcast<P, pp>(st[mp][pp]);
-    const float xo = (b[p] - dot[mp]) * __builtin_amdgcn_rcpf(d);
+    const float xo = (bm[mp] - dot[mp]) * __builtin_amdgcn_rcpf(d);  // x_p in its owner lane
     const float xp = grp_bcast<P, pp>(xo);
-    b[p] = xp;
     sfor<0, mp + 1>([&](auto Mm) {
       constexpr int m = decltype(Mm)::value;
       dot[m] = __builtin_fmaf(st[m][p - P * m], xp, dot[m]);  // row p of owned column P m + pi
     });
+    if constexpr (DUAL) {
+      const int j = ixs[sme * E + p];
+      sfor<0, KO / 4>([&](auto c) { u[c] += xp * Fr.row4(j, pi * KO + 4 * c); });
+    } else {
+      if constexpr (P == 1)
+        bm[mp] = xo;
+      else
+        bm[mp] = pi == pp ? xo : bm[mp];
+    }
   });
 
   if constexpr (P == 2) my_flags |= __builtin_amdgcn_mov_dpp(my_flags, 0xb1, 0xf, 0xf, true);
@@ -340,28 +365,12 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
     my_flags |= quad_xor2_i(my_flags);
   }
   const bool good = my_row >= 0 && my_cnt > 0 && !bad && my_flags == 0;
-  if constexpr (DUAL) {
-    // u = F_O^T a; lane pi of the group forms outputs [pi K/P, (pi+1) K/P)
-    constexpr int KO = K / P;
-    f4 u[KO / 4];
-    sfor<0, KO / 4>([&](auto c) { u[c] = f4{0.f, 0.f, 0.f, 0.f}; });
-    sfor<0, D>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      const int j = ixs[sme * E + i];
-      sfor<0, KO / 4>([&](auto c) { u[c] += b[i] * Fr.row4(j, pi * KO + 4 * c); });
-    });
-    if (my_row >= 0) {
+  if (my_row >= 0) {
+    if constexpr (DUAL) {
       float *out = X + my_row * K + pi * KO;
       sfor<0, KO / 4>([&](auto c) { *reinterpret_cast<f4 *>(out + 4 * c) = good ? u[c] : f4{0.f, 0.f, 0.f, 0.f}; });
-    }
-  } else {
-    if (my_row >= 0) {
-      sfor<0, M>([&](auto Mm) {
-        constexpr int m = decltype(Mm)::value;
-        float cand[P];
-        sfor<0, P>([&](auto k) { cand[k] = b[P * m + decltype(k)::value]; });
-        X[my_row * K + P * m + pi] = good ? pick<P>(cand, pi) : 0.f;
-      });
+    } else {
+      sfor<0, M>([&](auto m) { X[my_row * K + P * m + pi] = good ? bm[m] : 0.f; });
     }
   }
   if (status && my_row >= 0 && pi == 0)
@@ -376,14 +385,16 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
 
 // LDS budget of a block (bytes) and the factor matrix staged beside the per-wave buffers.
 constexpr int kLdsBytes = 160 * 1024;
-constexpr int kFactorLdsBytes = 64 * 1024;
+constexpr int kFactorLdsRows = 512;  // factor rows a block can stage (the fold-in has 480)
+template <int K>
+__host__ __device__ constexpr int factor_lds_bytes() { return kFactorLdsRows * K * 4; }
 template <int K, int P, int D>
 __host__ __device__ constexpr int wave_bytes() { return wave_lds_floats(P, D) * 4; }
 
 // Persistent kernel over the rows of classes c_lo..c_hi (contiguous in the bucketed list),
 // all solved at padded dimension D (dual) or k (primal).
-template <int K, int P, int D, bool DUAL, bool LDSF>
-__global__ __launch_bounds__(256) void k_solve_class(const float *__restrict__ F, int n,
+template <int K, int P, int D, bool DUAL, bool LDSF, int W, int OCC>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_waves_per_eu(OCC))) void k_solve_class(const float *__restrict__ F, int n,
                                                      const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                      const float *__restrict__ val, const RowRef *__restrict__ list,
                                                      const int64_t *__restrict__ cls, int c_lo, int c_hi, float lambda,
@@ -391,23 +402,23 @@ __global__ __launch_bounds__(256) void k_solve_class(const float *__restrict__ F
                                                      int32_t *__restrict__ status) {
   constexpr int SYS = 64 / P;
   constexpr int WL = wave_lds_floats(P, D);
-  constexpr int FL = LDSF ? kFactorLdsBytes / 4 + 256 : 4;  // + one wave instruction of tail
-  __shared__ __attribute__((aligned(16))) float lds_all[4 * WL + FL];
+  constexpr int FL = LDSF ? factor_lds_bytes<K>() / 4 + 256 : 4;  // + one wave instruction of tail
+  __shared__ __attribute__((aligned(16))) float lds_all[W * WL + FL];
   const int64_t start = cls[2 * c_lo];
   const int64_t count = cls[2 * c_hi] + cls[2 * c_hi + 1] - start;
   const int64_t end = start + count;
-  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if ((int64_t)blockIdx.x * (blockDim.x >> 6) * SYS >= count) return;  // block has no work (uniform)
+  const int64_t nw = (int64_t)gridDim.x * W;
+  const int64_t g0 = (int64_t)blockIdx.x * W + (threadIdx.x >> 6);
+  if ((int64_t)blockIdx.x * W * SYS >= count) return;  // block has no work (uniform)
   FRows<K, LDSF> Fr;
   if constexpr (LDSF) {
-    float *fl = lds_all + 4 * WL;
+    float *fl = lds_all + W * WL;
     // direct global -> LDS copies: one 16-byte chunk per lane, 1 KB per wave instruction;
     // LDS chunk (j, c) holds global chunk c ^ (j mod K/4) (the swizzle is an involution)
     constexpr int CH = K / 4;
     const int chunks = n * CH;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int base = w * 64; base < chunks; base += 4 * 64) {
+    for (int base = w * 64; base < chunks; base += W * 64) {
       const int e = base + lane;
       const int ee = e < chunks ? e : chunks - 1;  // tail lanes copy a valid chunk past the end
       const int jj = ee / CH, cc = ee % CH;
@@ -429,35 +440,43 @@ __global__ __launch_bounds__(256) void k_solve_class(const float *__restrict__ F
   RowRef cur = fetch(g0);
   for (int64_t g = g0; g * SYS < count; g += nw) {
     const RowRef nxt = fetch(g + nw);  // next group's records load while this group computes
-    solve_group<P, D, K, DUAL, LDSF>(Fr, n, cur, idx, val, lambda, weighted, X, status, wl);
+    // operand prefetch in the Gram loop when a single wave per SIMD has to hide the latency
+    solve_group<P, D, K, DUAL, LDSF, (OCC == 1 || D <= 12)>(Fr, n, cur, idx, val, lambda, weighted, X, status, wl);
     cur = nxt;
   }
 }
 
-// Launch the kernel of one size class with a persistent grid sized for m rows.
-template <int K, int P, int D, bool DUAL>
+// Launch the kernel of one size class with a persistent grid sized for m rows: blocks of W
+// waves (sharing one LDS copy of the factors), as many per CU as LDS and the register
+// budget of OCC waves per SIMD allow.
+template <int K, int P, int D, bool DUAL, int W = 4, int OCC = 1>
 open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n, const int64_t *ptr,
                          const int32_t *idx, const float *val, float lambda, int weighted, const RowRef *list,
                          const int64_t *cls, int c_lo, int c_hi, float *X, int32_t *status, int64_t m) {
+  static_assert(W >= 1 && W <= 16 && OCC >= 1 && OCC <= 8, "block shape");
   const int64_t groups = (m + 64 / P - 1) / (64 / P);
-  int64_t blocks = (groups + 3) / 4;
-  constexpr int waves_b = 4 * wave_bytes<K, P, D>();
-  constexpr bool fl_fits = waves_b + kFactorLdsBytes + 1024 <= kLdsBytes;
+  int64_t blocks = (groups + W - 1) / W;
+  constexpr int waves_b = W * wave_bytes<K, P, D>();
+  constexpr int flb = factor_lds_bytes<K>();
+  constexpr bool fl_fits = waves_b + flb + 1024 <= kLdsBytes;
+  static_assert(waves_b + 16 <= kLdsBytes, "per-wave buffers exceed LDS");
   // stage the factors in LDS when they fit beside the per-wave buffers
-  const bool fl = fl_fits && (int64_t)n * K * 4 <= kFactorLdsBytes;
-  const int per_cu = kLdsBytes / (waves_b + (fl ? kFactorLdsBytes : 16));
-  const int64_t cap = (int64_t)ctx->num_cu * (per_cu < 1 ? 1 : per_cu > 2 ? 2 : per_cu);
+  const bool fl = fl_fits && n <= kFactorLdsRows;
+  const int lds_cu = kLdsBytes / (waves_b + (fl ? flb + 1024 : 16));
+  const int reg_cu = 4 * OCC / W;  // waves a CU holds at OCC per SIMD, in blocks
+  int per_cu = lds_cu < reg_cu ? lds_cu : reg_cu;
+  const int64_t cap = (int64_t)ctx->num_cu * (per_cu < 1 ? 1 : per_cu);
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   if constexpr (fl_fits) {
     if (fl) {
-      OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, true>), dim3((unsigned)blocks), dim3(256), 0, F, n, ptr,
-                  idx, val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
+      OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, true, W, OCC>), dim3((unsigned)blocks), dim3(64 * W), 0,
+                  F, n, ptr, idx, val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
       return OPEN_OK;
     }
   }
-  OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, false>), dim3((unsigned)blocks), dim3(256), 0, F, n, ptr, idx,
-              val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
+  OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, false, W, OCC>), dim3((unsigned)blocks), dim3(64 * W), 0, F,
+              n, ptr, idx, val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
   return OPEN_OK;
 }
 
@@ -465,15 +484,63 @@ open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n,
   open_ctx *ctx, const float *F, int n, const int64_t *ptr, const int32_t *idx, const float *val, float lambda, \
       int weighted, const RowRef *list, const int64_t *cls, float *X, int32_t *status, int64_t m
 #define OPEN_TIER_PASS ctx, F, n, ptr, idx, val, lambda, weighted, list, cls
-// the kernels of each rank, each rank's group compiled in its own translation unit
-open_status classes_k8(OPEN_TIER_ARGS);
-open_status classes_k16(OPEN_TIER_ARGS);
-open_status classes_k32_small(OPEN_TIER_ARGS);
-open_status classes_k32_mid(OPEN_TIER_ARGS);
-open_status classes_k32_large(OPEN_TIER_ARGS);
-open_status classes_k32_primal(OPEN_TIER_ARGS);
-open_status classes_k64_small(OPEN_TIER_ARGS);
-open_status classes_k64_mid(OPEN_TIER_ARGS);
-open_status classes_k64_large(OPEN_TIER_ARGS);
+
+// ---------------------------------------------------------------- kernel variants
+// A kernel configuration in one integer: P lanes per system, W waves per block, and OCC
+// waves per SIMD that the register allocation must allow.
+constexpr int cfg(int P, int W, int OCC) { return P * 10000 + W * 100 + OCC; }
+
+// Launch configuration number `choice` of C... for one class group.
+template <int K, int D, bool DUAL, int... C>
+open_status launch_variant(int choice, const char *name, int c_lo, int c_hi, OPEN_TIER_ARGS) {
+  open_status st = OPEN_OK;
+  int i = 0;
+  bool done = false;
+  ((i++ == choice ? (void)(done = true, st = launch_class<K, C / 10000, D, DUAL, (C / 100) % 100, C % 100>(
+                                            name, OPEN_TIER_PASS, c_lo, c_hi, X, status, m))
+                  : (void)0),
+   ...);
+  if (!done) return fail(ctx, OPEN_E_INVALID, "kernel variant out of range");
+  return st;
+}
+
+// A group of size classes solved by one kernel, with its compiled variants.
+using group_fn = open_status (*)(int choice, OPEN_TIER_ARGS);
+struct ClassGroup {
+  const char *name;
+  int c_lo, c_hi;  // classes of the bucketed list it covers
+  int nvar;        // configurations compiled (variant 0 is the default)
+  group_fn fn;
+};
+
+// The class groups of rank k (8, 16, 32 or 64) and their number; nullptr for other ranks.
+const ClassGroup *class_groups(int k, int *count);
+
+#define OPEN_GROUP(NAME) open_status NAME(int choice, OPEN_TIER_ARGS)
+OPEN_GROUP(g_k8_d4);
+OPEN_GROUP(g_k8_d8);
+OPEN_GROUP(g_k8_primal);
+OPEN_GROUP(g_k16_d4);
+OPEN_GROUP(g_k16_d8);
+OPEN_GROUP(g_k16_d12);
+OPEN_GROUP(g_k16_d16);
+OPEN_GROUP(g_k16_primal);
+OPEN_GROUP(g_k32_d4);
+OPEN_GROUP(g_k32_d8);
+OPEN_GROUP(g_k32_d12);
+OPEN_GROUP(g_k32_d16);
+OPEN_GROUP(g_k32_d20);
+OPEN_GROUP(g_k32_d24);
+OPEN_GROUP(g_k32_d28);
+OPEN_GROUP(g_k32_d32);
+OPEN_GROUP(g_k32_primal);
+OPEN_GROUP(g_k64_d4);
+OPEN_GROUP(g_k64_d8);
+OPEN_GROUP(g_k64_d12);
+OPEN_GROUP(g_k64_d16);
+OPEN_GROUP(g_k64_d20);
+OPEN_GROUP(g_k64_d24);
+OPEN_GROUP(g_k64_d28);
+OPEN_GROUP(g_k64_d32);
 
 }  // namespace openk

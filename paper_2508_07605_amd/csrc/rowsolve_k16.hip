@@ -1,16 +1,32 @@
-// Ridge-solve kernels of one group of size classes, in their own translation unit.
+// Ridge-solve kernels of size-class groups, each with its compiled configurations
+// (lanes per system, waves per block, waves per SIMD); variant 0 is the default.
 #include "rowsolve.h"
 
 namespace openk {
 
-open_status classes_k16(OPEN_TIER_ARGS) {
-  open_status st;
-  if ((st = launch_class<16, 1, 4, true>("ridge_k16_d4", OPEN_TIER_PASS, 0, 1, X, status, m))) return st;
-  if ((st = launch_class<16, 1, 8, true>("ridge_k16_d8", OPEN_TIER_PASS, 2, 2, X, status, m))) return st;
-  if ((st = launch_class<16, 1, 12, true>("ridge_k16_d12", OPEN_TIER_PASS, 3, 3, X, status, m))) return st;
-  if ((st = launch_class<16, 1, 16, true>("ridge_k16_d16", OPEN_TIER_PASS, 4, 4, X, status, m))) return st;
-  if ((st = launch_class<16, 4, 16, false>("ridge_k16_primal", OPEN_TIER_PASS, 9, 15, X, status, m))) return st;
-  return OPEN_OK;
+OPEN_GROUP(g_k16_d4) {
+  return launch_variant<16, 4, true, cfg(1, 16, 4), cfg(4, 16, 4)>(choice, "ridge_k16_d4", 0, 1, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k16_d8) {
+  return launch_variant<16, 8, true, cfg(1, 12, 3), cfg(4, 16, 4)>(choice, "ridge_k16_d8", 2, 2, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k16_d12) {
+  return launch_variant<16, 12, true, cfg(1, 8, 2), cfg(4, 16, 4)>(choice, "ridge_k16_d12", 3, 3, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k16_d16) {
+  return launch_variant<16, 16, true, cfg(4, 16, 4), cfg(1, 4, 1)>(choice, "ridge_k16_d16", 4, 4, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k16_primal) {
+  return launch_variant<16, 16, false, cfg(4, 16, 4), cfg(4, 8, 2)>(choice, "ridge_k16_primal", 9, 15, OPEN_TIER_PASS, X,
+                       status, m);
 }
 
 }  // namespace openk

@@ -1,0 +1,12 @@
+// Ridge-solve kernels of size-class groups, each with its compiled configurations
+// (lanes per system, waves per block, waves per SIMD); variant 0 is the default.
+#include "rowsolve.h"
+
+namespace openk {
+
+OPEN_GROUP(g_k32_d16) {
+  return launch_variant<32, 16, true, cfg(4, 16, 4), cfg(4, 8, 2), cfg(1, 4, 1)>(choice, "ridge_k32_d16", 4, 4, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+}  // namespace openk

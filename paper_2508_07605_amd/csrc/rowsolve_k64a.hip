@@ -1,15 +1,27 @@
-// Ridge-solve kernels of one group of size classes, in their own translation unit.
+// Ridge-solve kernels of size-class groups, each with its compiled configurations
+// (lanes per system, waves per block, waves per SIMD); variant 0 is the default.
 #include "rowsolve.h"
 
 namespace openk {
 
-open_status classes_k64_small(OPEN_TIER_ARGS) {
-  open_status st;
-  if ((st = launch_class<64, 1, 4, true>("ridge_k64_d4", OPEN_TIER_PASS, 0, 1, X, status, m))) return st;
-  if ((st = launch_class<64, 1, 8, true>("ridge_k64_d8", OPEN_TIER_PASS, 2, 2, X, status, m))) return st;
-  if ((st = launch_class<64, 1, 12, true>("ridge_k64_d12", OPEN_TIER_PASS, 3, 3, X, status, m))) return st;
-  if ((st = launch_class<64, 1, 16, true>("ridge_k64_d16", OPEN_TIER_PASS, 4, 4, X, status, m))) return st;
-  return OPEN_OK;
+OPEN_GROUP(g_k64_d4) {
+  return launch_variant<64, 4, true, cfg(1, 16, 4), cfg(4, 16, 4)>(choice, "ridge_k64_d4", 0, 1, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k64_d8) {
+  return launch_variant<64, 8, true, cfg(1, 12, 3), cfg(4, 16, 4)>(choice, "ridge_k64_d8", 2, 2, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k64_d12) {
+  return launch_variant<64, 12, true, cfg(1, 8, 2), cfg(4, 16, 4)>(choice, "ridge_k64_d12", 3, 3, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k64_d16) {
+  return launch_variant<64, 16, true, cfg(4, 16, 4), cfg(1, 4, 1)>(choice, "ridge_k64_d16", 4, 4, OPEN_TIER_PASS, X,
+                       status, m);
 }
 
 }  // namespace openk

@@ -1,13 +1,17 @@
-// Ridge-solve kernels of one group of size classes, in their own translation unit.
+// Ridge-solve kernels of size-class groups, each with its compiled configurations
+// (lanes per system, waves per block, waves per SIMD); variant 0 is the default.
 #include "rowsolve.h"
 
 namespace openk {
 
-open_status classes_k64_mid(OPEN_TIER_ARGS) {
-  open_status st;
-  if ((st = launch_class<64, 2, 20, true>("ridge_k64_d20", OPEN_TIER_PASS, 5, 5, X, status, m))) return st;
-  if ((st = launch_class<64, 2, 24, true>("ridge_k64_d24", OPEN_TIER_PASS, 6, 6, X, status, m))) return st;
-  return OPEN_OK;
+OPEN_GROUP(g_k64_d20) {
+  return launch_variant<64, 20, true, cfg(4, 12, 3), cfg(2, 4, 1)>(choice, "ridge_k64_d20", 5, 5, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k64_d24) {
+  return launch_variant<64, 24, true, cfg(4, 12, 3), cfg(2, 4, 1)>(choice, "ridge_k64_d24", 6, 6, OPEN_TIER_PASS, X,
+                       status, m);
 }
 
 }  // namespace openk

@@ -1,13 +1,17 @@
-// Ridge-solve kernels of one group of size classes, in their own translation unit.
+// Ridge-solve kernels of size-class groups, each with its compiled configurations
+// (lanes per system, waves per block, waves per SIMD); variant 0 is the default.
 #include "rowsolve.h"
 
 namespace openk {
 
-open_status classes_k64_large(OPEN_TIER_ARGS) {
-  open_status st;
-  if ((st = launch_class<64, 4, 28, true>("ridge_k64_d28", OPEN_TIER_PASS, 7, 7, X, status, m))) return st;
-  if ((st = launch_class<64, 4, 32, true>("ridge_k64_d32", OPEN_TIER_PASS, 8, 8, X, status, m))) return st;
-  return OPEN_OK;
+OPEN_GROUP(g_k64_d28) {
+  return launch_variant<64, 28, true, cfg(4, 8, 2), cfg(4, 4, 1)>(choice, "ridge_k64_d28", 7, 7, OPEN_TIER_PASS, X,
+                       status, m);
+}
+
+OPEN_GROUP(g_k64_d32) {
+  return launch_variant<64, 32, true, cfg(4, 8, 2), cfg(4, 4, 1)>(choice, "ridge_k64_d32", 8, 8, OPEN_TIER_PASS, X,
+                       status, m);
 }
 
 }  // namespace openk

@@ -33,6 +33,10 @@ SIGNATURES = {
     "open_profile": (_I32, [_P, _I32]),
     "open_profile_read": (_I32, [_P, _P, _P, _P, _I32, _I32]),
     "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
+    "open_tune_info": (_I32, [_I32, _P, _P, _I32]),
+    "open_tune_get": (_I32, [_P, _I32, _P, _I32]),
+    "open_tune_set": (_I32, [_P, _I32, _P, _I32]),
+    "open_autotune": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P, _I32, _P]),
     "open_csr_to_csc": (_I32, [_P, _I64, _I32, _P, _P, _P, _P, _P, _P]),
     "open_fit": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
     "open_objective": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _F32, _I32, _P]),
@@ -132,6 +136,17 @@ class Context:
             raise OpenError(OPEN_E_DEVICE, "open_profile_read failed")
         return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(n, cap))}
 
+    def tune_get(self, k):
+        """Chosen kernel variant per class group of rank k."""
+        ng = len(open_tune_info(k))
+        buf = (ctypes.c_int8 * ng)()
+        self.check(lib().open_tune_get(self.handle, k, buf, ng))
+        return list(buf)
+
+    def tune_set(self, k, choice):
+        buf = (ctypes.c_int8 * len(choice))(*choice)
+        self.check(lib().open_tune_set(self.handle, k, buf, len(choice)))
+
     def close(self):
         if getattr(self, "handle", None):
             lib().open_destroy(self.handle)
@@ -155,6 +170,37 @@ def open_foldin(ctx, F, row_ptr, col, val, lam, weighted=True, U_out=None, row_s
                                 _dev(U_out, torch.float32, "U_out", m * k),
                                 _dev(row_status, torch.int32, "row_status", m)))
     return U_out
+
+
+def open_tune_info(k):
+    """[(group kernel name, variants compiled)] of rank k."""
+    cap = 32
+    names = (ctypes.c_char_p * cap)()
+    nvar = (ctypes.c_int32 * cap)()
+    n = lib().open_tune_info(k, names, nvar, cap)
+    if n < 0:
+        raise OpenError(OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64")
+    return [(names[i].decode(), nvar[i]) for i in range(min(n, cap))]
+
+
+def open_autotune(ctx, F, row_ptr, col, val, lam, weighted=True, reps=5, U_out=None, row_status=None):
+    """Time every kernel variant on this batch, keep the fastest per class group in ctx.
+    Returns (U_out, {group name: [ms per launch of each variant, None if untimed]})."""
+    n, k = F.shape
+    m = row_ptr.numel() - 1
+    groups = open_tune_info(k)
+    if U_out is None:
+        U_out = torch.empty((m, k), dtype=torch.float32, device=F.device)
+    ms = (ctypes.c_double * (4 * len(groups)))()
+    ctx.check(lib().open_autotune(ctx.handle, _dev(F, torch.float32, "F"), n, k, m,
+                                  _dev(row_ptr, torch.int64, "row_ptr", m + 1), _dev(col, torch.int32, "col"),
+                                  _dev(val, torch.float32, "val"), float(lam), int(bool(weighted)),
+                                  _dev(U_out, torch.float32, "U_out", m * k),
+                                  _dev(row_status, torch.int32, "row_status", m), int(reps), ms))
+    table = {}
+    for g, (name, nv) in enumerate(groups):
+        table[name] = [ms[4 * g + v] if ms[4 * g + v] >= 0 else None for v in range(nv)]
+    return U_out, table
 
 
 def open_csr_to_csc(ctx, row_ptr, col, val, n):
@@ -302,6 +348,17 @@ class Surrogate:
                                              _dev(rho, torch.float32, "rho", m),
                                              ctypes.byref(nf) if count else None))
         return U_out, (nf.value if count else None)
+
+    def tune_get(self, k):
+        """Chosen kernel variant per class group of rank k."""
+        ng = len(open_tune_info(k))
+        buf = (ctypes.c_int8 * ng)()
+        self.check(lib().open_tune_get(self.handle, k, buf, ng))
+        return list(buf)
+
+    def tune_set(self, k, choice):
+        buf = (ctypes.c_int8 * len(choice))(*choice)
+        self.check(lib().open_tune_set(self.handle, k, buf, len(choice)))
 
     def close(self):
         if getattr(self, "handle", None):

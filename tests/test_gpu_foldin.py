@@ -123,3 +123,69 @@ def test_full_size_sampled(ctx):
     report("foldin full-size sample", e)
     assert e.max() <= TOL
     assert np.isfinite(U).all()
+
+
+@pytest.mark.parametrize("k,n,maxc", [(8, 120, 120), (16, 120, 120), (32, 480, 480), (32, 600, 600),
+                                      (64, 480, 32)])
+def test_every_kernel_variant(ctx, k, n, maxc):
+    # each compiled configuration of each size-class kernel, selected through the tuning
+    # table, against the oracle; n = 600 exceeds the factor rows a block stages in LDS
+    groups = native.open_tune_info(k)
+    r = np.random.default_rng(300 + k + n)
+    counts = np.concatenate([np.repeat(np.arange(0, maxc + 1), 2), r.integers(0, maxc + 1, size=301)])
+    r.shuffle(counts)
+    rp, col, val = csr_from_counts(r, counts, n)
+    V = (r.normal(size=(n, k)) * 0.3).astype(np.float32)
+    ref, ref_st = oracle.ridge_rows(rp, col, val, V, 0.05, True)
+    default = ctx.tune_get(k)
+    try:
+        for v in range(max(nv for _, nv in groups)):
+            ctx.tune_set(k, [min(v, nv - 1) for _, nv in groups])
+            U, st = run_gpu(ctx, V, rp, col, val, 0.05)
+            assert np.array_equal(st, ref_st)
+            e = rel_err(U, ref)[counts > 0]
+            report("variant %d k%d n%d" % (v, k, n), e)
+            assert e.max() <= TOL
+    finally:
+        ctx.tune_set(k, default)
+
+
+def test_tune_table_rejects_bad_choice(ctx):
+    groups = native.open_tune_info(32)
+    before = ctx.tune_get(32)
+    with pytest.raises(native.OpenError):
+        ctx.tune_set(32, [nv for _, nv in groups])  # one past the last variant everywhere
+    with pytest.raises(native.OpenError):
+        ctx.tune_set(32, before[:-1])  # wrong length
+    assert ctx.tune_get(32) == before
+
+
+def test_autotune_result_and_cache(ctx, tmp_path):
+    from paper_2508_07605_amd import autotune
+    grid = synth.grid_of("foldin")
+    V = synth.setting_factors(3, grid, 32, m_ref=2048)
+    rows = synth.draw_rows(3, grid, 30_011, ("uniform", 4, 24), seed=13)
+    dV, drp, dcol, dval = dev(V), dev(rows.row_ptr), dev(rows.col), dev(rows.val)
+    st = torch.full((rows.m,), -7, dtype=torch.int32, device="cuda")
+    U, table = native.open_autotune(ctx, dV, drp, dcol, dval, 0.05, True, reps=2, row_status=st)
+    print("autotune ms per launch:", table)
+    ref, ref_st = oracle.ridge_rows(rows.row_ptr, rows.col, rows.val, V, 0.05, True)
+    assert np.array_equal(st.cpu().numpy(), ref_st)
+    assert rel_err(U.cpu().numpy().astype(np.float64), ref).max() <= TOL
+    groups = native.open_tune_info(32)
+    choice = ctx.tune_get(32)
+    for (name, nv), c in zip(groups, choice):
+        assert 0 <= c < nv
+        timed = table[name]
+        if any(t is not None for t in timed):  # populated group: the fastest variant was kept
+            assert timed[c] == min(t for t in timed if t is not None)
+        else:
+            assert c == 0
+    # the cache restores the choice in a fresh context
+    path = str(tmp_path / "tune.json")
+    got, tab = autotune.tune(ctx, dV, drp, dcol, dval, 0.05, reps=1, path=path, force=True)
+    c2 = native.Context(0)
+    try:
+        assert autotune.load(c2, 32, path) == got == c2.tune_get(32)
+    finally:
+        c2.close()
