@@ -58,32 +58,27 @@ __device__ __forceinline__ float pick(const float *v, int pi) {
 }
 
 // ---------------------------------------------------------------- factor-row access
-// F rows from LDS or from global memory through a bounds-checked buffer resource.  In LDS
-// the 16-byte chunks of row j are stored in the order c ^ (j mod K/4), so lanes reading the
-// same chunk of different rows hit different banks.  A row index of -1 reads as zeros.
+// F rows from LDS or from global memory through a bounds-checked buffer resource.  In LDS a
+// row occupies K + 4 floats (one pad chunk, so that lanes reading the same chunk of different
+// rows spread over the banks) and a row of zeros sits just before row 0: the row index -1 of
+// padded and rejected entries reads zeros without a test, as it does from the buffer
+// resource (a negative offset is out of range there).
 template <int K, bool LDS>
 struct FRows {
-  static constexpr int CH = K / 4;  // 16-byte chunks per row
-  const float *lds;
+  static constexpr int PS = K + 4;  // LDS row pitch in floats
+  const float *lds;                 // row 0 (row -1 is the zero row)
   __amdgpu_buffer_rsrc_t rs;
-  __device__ static __forceinline__ int slot(int j, int c) { return j * K + 4 * (c ^ (j & (CH - 1))); }
   __device__ __forceinline__ f4 row4(int j, int k0) const {
-    if constexpr (LDS) {
-      const int jj = j >= 0 ? j : 0;
-      const f4 v = *reinterpret_cast<const f4 *>(lds + slot(jj, k0 / 4));
-      return j >= 0 ? v : f4{0.f, 0.f, 0.f, 0.f};
-    } else {
+    if constexpr (LDS)
+      return *reinterpret_cast<const f4 *>(lds + j * PS + k0);
+    else
       return bload_f4(rs, (j * K + k0) * 4);
-    }
   }
   __device__ __forceinline__ float row1(int j, int k) const {
-    if constexpr (LDS) {
-      const int jj = j >= 0 ? j : 0;
-      const float v = lds[slot(jj, k / 4) + (k & 3)];
-      return j >= 0 ? v : 0.f;
-    } else {
+    if constexpr (LDS)
+      return lds[j * PS + k];
+    else
       return bload_f32(rs, (j * K + k) * 4);
-    }
   }
 };
 
@@ -386,8 +381,9 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
 // LDS budget of a block (bytes) and the factor matrix staged beside the per-wave buffers.
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kFactorLdsRows = 512;  // factor rows a block can stage (the fold-in has 480)
+// the zero row, kFactorLdsRows rows at pitch K + 4, and one wave instruction (64 slots) of tail
 template <int K>
-__host__ __device__ constexpr int factor_lds_bytes() { return kFactorLdsRows * K * 4; }
+__host__ __device__ constexpr int factor_lds_bytes() { return ((kFactorLdsRows + 1) * (K + 4) + 256) * 4; }
 template <int K, int P, int D>
 __host__ __device__ constexpr int wave_bytes() { return wave_lds_floats(P, D) * 4; }
 
@@ -402,7 +398,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_wa
                                                      int32_t *__restrict__ status) {
   constexpr int SYS = 64 / P;
   constexpr int WL = wave_lds_floats(P, D);
-  constexpr int FL = LDSF ? factor_lds_bytes<K>() / 4 + 256 : 4;  // + one wave instruction of tail
+  constexpr int FL = LDSF ? factor_lds_bytes<K>() / 4 : 4;
   __shared__ __attribute__((aligned(16))) float lds_all[W * WL + FL];
   const int64_t start = cls[2 * c_lo];
   const int64_t count = cls[2 * c_hi] + cls[2 * c_hi + 1] - start;
@@ -412,22 +408,23 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_wa
   if ((int64_t)blockIdx.x * W * SYS >= count) return;  // block has no work (uniform)
   FRows<K, LDSF> Fr;
   if constexpr (LDSF) {
+    // [zero row][n rows at pitch PS][tail]: direct global -> LDS copies, one 16-byte slot
+    // per lane and 1 KB per wave instruction; a row's pad slot copies its chunk 0, and the
+    // lanes of the last instruction past the end copy the last chunk into the tail
+    constexpr int PS = K + 4, CH = K / 4, SL = CH + 1;
     float *fl = lds_all + W * WL;
-    // direct global -> LDS copies: one 16-byte chunk per lane, 1 KB per wave instruction;
-    // LDS chunk (j, c) holds global chunk c ^ (j mod K/4) (the swizzle is an involution)
-    constexpr int CH = K / 4;
-    const int chunks = n * CH;
+    const int slots = n * SL;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int base = w * 64; base < chunks; base += W * 64) {
-      const int e = base + lane;
-      const int ee = e < chunks ? e : chunks - 1;  // tail lanes copy a valid chunk past the end
-      const int jj = ee / CH, cc = ee % CH;
-      __builtin_amdgcn_global_load_lds(F + (int64_t)jj * K + 4 * (cc ^ (jj & (CH - 1))),
-                                       (__attribute__((address_space(3))) void *)(fl + 4 * base), 16, 0, 0);
+    for (int base = w * 64; base < slots; base += W * 64) {
+      const int e = base + lane < slots ? base + lane : slots - 2;  // slots - 2: last data chunk
+      const int jj = e / SL, cc = e % SL;
+      __builtin_amdgcn_global_load_lds(F + (int64_t)jj * K + 4 * (cc < CH ? cc : 0),
+                                       (__attribute__((address_space(3))) void *)(fl + PS + 4 * base), 16, 0, 0);
     }
+    if (threadIdx.x < PS) fl[threadIdx.x] = 0.f;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    Fr.lds = fl;
+    Fr.lds = fl + PS;
   } else {
     Fr.rs = make_rsrc(F, (uint64_t)n * K * sizeof(float));
   }
@@ -458,11 +455,11 @@ open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n,
   int64_t blocks = (groups + W - 1) / W;
   constexpr int waves_b = W * wave_bytes<K, P, D>();
   constexpr int flb = factor_lds_bytes<K>();
-  constexpr bool fl_fits = waves_b + flb + 1024 <= kLdsBytes;
+  constexpr bool fl_fits = waves_b + flb <= kLdsBytes;
   static_assert(waves_b + 16 <= kLdsBytes, "per-wave buffers exceed LDS");
   // stage the factors in LDS when they fit beside the per-wave buffers
   const bool fl = fl_fits && n <= kFactorLdsRows;
-  const int lds_cu = kLdsBytes / (waves_b + (fl ? flb + 1024 : 16));
+  const int lds_cu = kLdsBytes / (waves_b + (fl ? flb : 16));
   const int reg_cu = 4 * OCC / W;  // waves a CU holds at OCC per SIMD, in blocks
   int per_cu = lds_cu < reg_cu ? lds_cu : reg_cu;
   const int64_t cap = (int64_t)ctx->num_cu * (per_cu < 1 ? 1 : per_cu);
