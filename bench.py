@@ -54,6 +54,169 @@ def kernel_of_counts(n, k):
     return out
 
 
+def surrogate_leg(args, ctx, dV, drp, dcol, dval, m, steps, warmup, log):
+    """Surrogate fold-in (MLP + ALS fallback on rows whose observed-entry RMS residual exceeds
+    tau): train on 2M ALS fold-in targets of new draws, then time surrogate+fallback on the
+    benchmark rows, and the same with an untrained network (which falls back almost everywhere)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    c = synth.CONFIGS["surrogate"]
+    grid = synth.grid_of("surrogate")
+    n, k, lam, tau = grid.n, c["k"], c["lam"], c["tau"]
+    dev = dV.device
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    t0 = time.time()
+    tr = synth.draw_rows(c["cfg_id"], grid, c["m_train"], c["counts"], seed=c["train_seed"])
+    trp, tcol, tval = to(tr.row_ptr), to(tr.col), to(tr.val)
+    target = native.open_foldin(ctx, dV, trp, tcol, tval, lam, True)
+    torch.cuda.synchronize()
+    log("surrogate: %d training rows and their ALS targets in %.1f s" % (tr.m, time.time() - t0))
+
+    init = np.concatenate([np.asarray(p, np.float32).reshape(-1)
+                           for p in synth.mlp_init(c["cfg_id"], (2 * n, c["hidden"], c["hidden"], k), seed=1)])
+    net = native.Surrogate(ctx, n, k, c["hidden"], init=init)
+    untrained = native.Surrogate(ctx, n, k, c["hidden"], init=init)
+    B = c["batch"]
+    per_epoch = (tr.m + B - 1) // B
+    total = int(round(args.surrogate_epochs * per_epoch))
+    gen = torch.Generator(device=dev).manual_seed(7)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.time()
+    done = 0
+    while done < total:
+        perm = torch.randperm(tr.m, generator=gen, device=dev)
+        for b in range(per_epoch):
+            if done == total:
+                break
+            net.train_step(trp, tcol, tval, target, perm[b * B:(b + 1) * B], c["lr"], loss_out=loss)
+            done += 1
+            if done % 100 == 0 or done == total:
+                hist.append((done, float(loss.item())))
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    log("surrogate: %d Adam steps (%.2f epochs) in %.1f s, loss %s" % (total, total / per_epoch, train_s,
+                                                                     hist[::max(1, len(hist) // 6)] + hist[-1:]))
+    del trp, tcol, tval, target
+
+    U = torch.empty((m, k), dtype=torch.float32, device=dev)
+    used = torch.empty(m, dtype=torch.uint8, device=dev)
+
+    def timed(model):
+        for _ in range(warmup):
+            model.foldin(dV, drp, dcol, dval, tau, lam, True, U_out=U, used_fallback=used, count=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            model.foldin(dV, drp, dcol, dval, tau, lam, True, U_out=U, used_fallback=used, count=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        _, nf = model.foldin(dV, drp, dcol, dval, tau, lam, True, U_out=U, used_fallback=used)
+        return ms, nf
+
+    ms0, nf0 = timed(untrained)
+    ms, nf = timed(net)
+    out = {
+        "rows_per_s": m / (ms * 1e-3), "ms_per_step": ms, "fallback_fraction": nf / m,
+        "untrained_rows_per_s": m / (ms0 * 1e-3), "untrained_fallback_fraction": nf0 / m,
+        "train_steps": total, "train_epochs": round(total / per_epoch, 3), "train_rows": tr.m, "batch": B,
+        "train_seconds": round(train_s, 2), "final_loss": hist[-1][1] if hist else None, "tau": tau,
+        "network": "%d-%d-%d-%d bf16 weights, fp32 accumulate" % (2 * n, c["hidden"], c["hidden"], k),
+    }
+    untrained.close()
+    net.close()
+    return out, U
+
+
+def predict_leg(ctx, steps, warmup, log):
+    """Fused predict + Algorithm 2 selection on 2M apps x 1920 settings (48 x 40 caps), rank 64:
+    the prediction tile U V^T on FP32 MFMA and the per-row selection, P not written."""
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    c = synth.CONFIGS["large"]
+    grid = synth.grid_of("large")
+    k, m = c["k"], c["m"]
+    t0 = time.time()
+    V = synth.setting_factors(c["cfg_id"], grid, k)
+    U = synth.latent_rows(c["cfg_id"], grid, V, m, seed=0)
+    dev = torch.device("cuda", 0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    dU, dV = to(U), to(V)
+    cc, cg = to(grid.cpu_w.astype(np.float32)), to(grid.gpu_w.astype(np.float32))
+    bi = torch.empty(m, dtype=torch.int32, device=dev)
+    bs = torch.empty(m, dtype=torch.float32, device=dev)
+    log("predict: inputs %d x %d, rank %d in %.1f s" % (m, grid.n, k, time.time() - t0))
+    run = lambda: native.open_predict(ctx, dU, dV, cc, cg, grid.base, c["gamma"], best_idx=bi, best_saving=bs)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flops = 2.0 * k * grid.n * m
+    byts = (4.0 * k + 8.0) * m
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": "predict + Alg. 2 selection: %d apps x %d settings (48 x 40 caps), rank %d, gamma %g"
+                        % (m, grid.n, k, c["gamma"]),
+            "rows_per_s": m / (ms * 1e-3), "ms_per_step": ms,
+            "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops,
+                         "algorithmic_bytes": byts, "hbm_gbs": round(byts / (ms * 1e-3) / 1e9, 1)}}
+
+
+def fit_leg(args, ctx, log):
+    """ALS-WR fit on 200k apps x 480 settings, truncated Zipf(1.2) observed counts on [3, 480]
+    (12.7M observed entries), rank 32, weighted lambda 0.05: time per sweep (rows, then
+    columns), objective after the timed sweeps."""
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    c = synth.CONFIGS["fit"]
+    grid = synth.grid_of("fit")
+    k, lam = c["k"], c["lam"]
+    t0 = time.time()
+    rows = synth.draw_rows(c["cfg_id"], grid, c["m"], c["counts"], seed=0)
+    U0, V0 = synth.init_factors(c["cfg_id"], rows.m, grid.n, k)
+    dev = torch.device("cuda", 0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    drp, dcol, dval = to(rows.row_ptr), to(rows.col), to(rows.val)
+    dU, dV = to(U0), to(V0)
+    log("fit: %d rows, %d nnz in %.1f s" % (rows.m, rows.nnz, time.time() - t0))
+    native.open_fit(ctx, drp, dcol, dval, dU, dV, lam, 1)  # warm-up sweep (workspaces, code)
+    torch.cuda.synchronize()
+    S = args.fit_sweeps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    native.open_fit(ctx, drp, dcol, dval, dU, dV, lam, S)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / S
+    obj = native.open_objective(ctx, drp, dcol, dval, dU, dV, lam)
+    ccount = np.bincount(rows.col, minlength=grid.n)
+    flops = float(row_flops(rows.counts(), k).sum() + row_flops(ccount, k).sum())
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": "ALS-WR fit: %d apps x %d settings, Zipf(1.2) counts on [3, 480], %d nnz, rank %d, "
+                        "weighted lambda %g" % (rows.m, grid.n, rows.nnz, k, lam),
+            "ms_per_sweep": ms, "sweeps_timed": S, "objective_after": obj,
+            "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +229,12 @@ def main():
                     help="also run a 256 MiB device copy (reference kernel for HBM counter scaling)")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel variants")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate (MLP + fallback) leg")
+    ap.add_argument("--no-predict", action="store_true", help="skip the predict + selection leg")
+    ap.add_argument("--no-fit", action="store_true", help="skip the ALS fit leg")
+    ap.add_argument("--fit-sweeps", type=int, default=3, help="timed ALS sweeps in the fit leg")
+    ap.add_argument("--surrogate-epochs", type=float, default=2.0,
+                    help="training epochs over the 2M ALS fold-in targets (batch 4096, Adam 1e-3)")
     ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuned kernel variants")
     args = ap.parse_args()
 
@@ -177,6 +346,23 @@ def main():
         "roofline": roofline,
     }
 
+    log = lambda msg: print("bench: " + msg, file=sys.stderr, flush=True)
+    if not args.no_predict:
+        out["predict_select"] = predict_leg(ctx, args.steps, args.warmup, log)
+        log("predict+select %.3e rows/s, %.1f TFLOP/s" % (out["predict_select"]["rows_per_s"],
+                                                          out["predict_select"]["roofline"]["achieved"]))
+    if not args.no_fit:
+        out["fit"] = fit_leg(args, ctx, log)
+        log("fit %.3f ms/sweep, %.1f TFLOP/s" % (out["fit"]["ms_per_sweep"], out["fit"]["roofline"]["achieved"]))
+    U_sur = None
+    if not args.no_surrogate:
+        log = lambda msg: print("bench: " + msg, file=sys.stderr, flush=True)
+        sur, U_sur = surrogate_leg(args, ctx, dV, drp, dcol, dval, m, args.steps, args.warmup, log)
+        out["surrogate"] = sur
+        log("surrogate+fallback %.3e rows/s (fallback %.3f), untrained %.3e rows/s (fallback %.3f)"
+            % (sur["rows_per_s"], sur["fallback_fraction"], sur["untrained_rows_per_s"],
+               sur["untrained_fallback_fraction"]))
+
     # accuracy: both fold-ins against the noiseless truth on unobserved settings of sampled rows
     if not args.no_cpu_baseline:
         import oracle
@@ -205,6 +391,12 @@ def main():
         rmse_g = float(np.sqrt((((Ug @ Vd.T) - T)[~obs] ** 2).mean()))
         rmse_o = float(np.sqrt((((Uo @ Vd.T) - T)[~obs] ** 2).mean()))
         e = np.linalg.norm(Ug - Uo, axis=1) / np.linalg.norm(Uo, axis=1)
+        if U_sur is not None:
+            Us = U_sur[torch.from_numpy(ev).to(dev)].cpu().numpy().astype(np.float64)
+            rmse_s = float(np.sqrt((((Us @ Vd.T) - T)[~obs] ** 2).mean()))
+            out["surrogate"].update({"rmse": rmse_s, "rmse_gap_vs_oracle_als": abs(rmse_s - rmse_o),
+                                     "pred_rmse_vs_oracle_als": float(np.sqrt(((((Us - Uo) @ Vd.T))[~obs] ** 2)
+                                                                              .mean()))})
         out["accuracy"] = {"rows": len(ev), "rmse_gpu": rmse_g, "rmse_oracle": rmse_o,
                            "rmse_gap": abs(rmse_g - rmse_o), "max_rel_err_vs_oracle": float(e.max()),
                            "accuracy_pct_1_minus_mape": float(100 * (1 - np.abs(((Ug @ Vd.T) - T)[~obs] /

@@ -180,10 +180,13 @@ open_status open_sync(open_ctx *ctx) {
   return OPEN_OK;
 }
 
-// Shared front half of open_foldin and open_autotune: validation and bucketing.
+// Shared front half of open_foldin and open_autotune: validation and bucketing.  Rows can
+// reach the split-K length only when F has at least kSplitMin rows (column indices are
+// unique within a row); then the total entry count is read back to size its work.
 static open_status foldin_prepare(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m,
                                   const int64_t *row_ptr, const int32_t *col, const float *val, float lambda,
-                                  float *U_out, RowRef **list, int64_t **cls) {
+                                  float *U_out, RowRef **list, int64_t **cls, int64_t *nnz_split) {
+  *nnz_split = -1;
   if (!rank_ok(k)) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
   if (n <= 0 || !F) return fail(ctx, OPEN_E_INVALID, "factor matrix must be non-empty");
   if (!(lambda >= 0.0f) || !isfinite(lambda)) return fail(ctx, OPEN_E_INVALID, "lambda must be finite and >= 0");
@@ -192,16 +195,23 @@ static open_status foldin_prepare(open_ctx *ctx, const float *F, int32_t n, int3
   if (m > 0 && !U_out) return fail(ctx, OPEN_E_INVALID, "output must not be NULL");
   if (m == 0) return OPEN_OK;
   OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  if ((st = bucket_rows(ctx, m, row_ptr, k, list, cls, INT64_MAX))) return st;
+  if (n >= kSplitMin) {
+    int64_t *h;
+    if ((st = pinned_get(ctx, sizeof(int64_t), (void **)&h))) return st;
+    OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    *nnz_split = *h;
+  }
+  if ((st = bucket_rows(ctx, m, row_ptr, k, list, cls, *nnz_split >= 0 ? kSplitMin : INT64_MAX))) return st;
   if (k == 64) {
-    // rank 64 solves only the dual form (n_i <= 32) in this build
+    // rank 64 solves the dual form (n_i <= 32) and the split-K form (n_i >= kSplitMin)
     int64_t *h;
     if ((st = pinned_get(ctx, sizeof(int64_t) * 2 * kNumClasses, (void **)&h))) return st;
     OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, *cls, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToHost, ctx->stream));
     OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     int64_t big = 0;
-    for (int c = 9; c < kNumClasses; ++c) big += h[2 * c + 1];
-    if (big) return fail(ctx, OPEN_E_UNSUPPORTED, "rank 64 with more than 32 observed entries in a row");
+    for (int c = 9; c < kSplitClass; ++c) big += h[2 * c + 1];
+    if (big) return fail(ctx, OPEN_E_UNSUPPORTED, "rank 64 with 33 to 1023 observed entries in a row");
   }
   return OPEN_OK;
 }
@@ -211,10 +221,13 @@ open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int
                         int32_t *row_status) {
   if (!ctx) return OPEN_E_INVALID;
   RowRef *list = nullptr;
-  int64_t *cls = nullptr;
-  open_status st = foldin_prepare(ctx, F, n, k, m, row_ptr, col, val, lambda, U_out, &list, &cls);
+  int64_t *cls = nullptr, nnz = -1;
+  open_status st = foldin_prepare(ctx, F, n, k, m, row_ptr, col, val, lambda, U_out, &list, &cls, &nnz);
   if (st || m == 0) return st;
-  return rowsolve_launch(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m);
+  if ((st = rowsolve_launch(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m)))
+    return st;
+  if (nnz >= 0) return splitk_launch(ctx, F, n, k, col, val, lambda, weighted, list, cls, U_out, row_status, m, nnz);
+  return OPEN_OK;
 }
 
 int32_t open_tune_info(int32_t k, const char **names, int32_t *nvar, int32_t max) {
@@ -255,11 +268,14 @@ open_status open_autotune(open_ctx *ctx, const float *F, int32_t n, int32_t k, i
   if (!ctx) return OPEN_E_INVALID;
   if (reps < 1) return fail(ctx, OPEN_E_INVALID, "reps must be >= 1");
   RowRef *list = nullptr;
-  int64_t *cls = nullptr;
-  open_status st = foldin_prepare(ctx, F, n, k, m, row_ptr, col, val, lambda, U_out, &list, &cls);
+  int64_t *cls = nullptr, nnz = -1;
+  open_status st = foldin_prepare(ctx, F, n, k, m, row_ptr, col, val, lambda, U_out, &list, &cls, &nnz);
   if (st || m == 0) return st;
-  return rowsolve_autotune(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m, reps,
-                           ms_out);
+  if ((st = rowsolve_autotune(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m,
+                              reps, ms_out)))
+    return st;
+  if (nnz >= 0) return splitk_launch(ctx, F, n, k, col, val, lambda, weighted, list, cls, U_out, row_status, m, nnz);
+  return OPEN_OK;
 }
 
 }  // extern "C"

@@ -111,7 +111,7 @@ struct open_ctx {
   // grow-only device workspaces, indexed by purpose
   enum {
     WS_HIST, WS_CLS, WS_LIST, WS_CSC_PTR, WS_CSC_IDX, WS_CSC_VAL, WS_RED, WS_SPLIT, WS_MISC, WS_FLAG, WS_OBJ,
-    WS_PRED, WS_COUNT
+    WS_PRED, WS_SPLIT_START, WS_SPLIT_PART, WS_SPLIT_FLAG, WS_COUNT
   };
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};
@@ -178,7 +178,8 @@ struct RowRef {
 // Row classification + stable counting sort; fills list[m] (row ids grouped by class) and
 // cls[2*kNumClasses] = {start, count} per class, on the device.
 constexpr int kNumClasses = 17;
-constexpr int kSplitClass = 16;  // rows solved by the split-K column path
+constexpr int kSplitClass = 16;  // rows solved by the split-K path
+constexpr int64_t kSplitMin = 1024;  // observations from which a row takes the split-K path
 open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, RowRef **list, int64_t **cls,
                         int64_t split_min, const uint8_t *mask = nullptr);
 // Column view on the device (stable counting sort); entries with a column outside [0, n) are dropped.
@@ -188,6 +189,10 @@ open_status csr_to_csc_dev(open_ctx *ctx, int64_t m, int n, const int64_t *row_p
 open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const int64_t *row_ptr, const int32_t *col,
                             const float *val, float lambda, int weighted, const RowRef *list, const int64_t *cls,
                             float *X, int32_t *status, int64_t m);
+// Split-K solve of the rows of class kSplitClass (F has nF rows, nnz bounds the work).
+open_status splitk_launch(open_ctx *ctx, const float *F, int nF, int k, const int32_t *idx, const float *val,
+                          float lambda, int weighted, const RowRef *list, const int64_t *cls, float *X,
+                          int32_t *status, int64_t m, int64_t nnz);
 // Kernel variants: at most kMaxVariants per class group; rank_index maps 8/16/32/64 to 0..3.
 constexpr int kMaxVariants = 4;
 int rank_index(int k);

@@ -421,14 +421,14 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
     if ((st = csr_to_csc_dev(ctx, m, n, row_ptr, col, val, cp, ri, cv))) break;
     RowRef *l;
     int64_t *c;
-    if ((st = bucket_rows(ctx, m, row_ptr, k, &l, &c, INT64_MAX))) break;
+    if ((st = bucket_rows(ctx, m, row_ptr, k, &l, &c, kSplitMin))) break;
     if (hipMemcpyAsync(list_r, l, sizeof(RowRef) * m, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
         hipMemcpyAsync(cls_r, c, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToDevice, ctx->stream) !=
             hipSuccess) {
       st = fail(ctx, OPEN_E_DEVICE, "copy");
       break;
     }
-    if ((st = bucket_rows(ctx, n, cp, k, &l, &c, INT64_MAX))) break;
+    if ((st = bucket_rows(ctx, n, cp, k, &l, &c, kSplitMin))) break;
     if (hipMemcpyAsync(list_c, l, sizeof(RowRef) * n, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
         hipMemcpyAsync(cls_c, c, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToDevice, ctx->stream) !=
             hipSuccess) {
@@ -445,20 +445,23 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
         break;
       }
       int64_t big = 0;
-      for (int cc = 9; cc < kNumClasses; ++cc) big += h[2 * cc + 1] + h[2 * kNumClasses + 2 * cc + 1];
+      for (int cc = 9; cc < kSplitClass; ++cc) big += h[2 * cc + 1] + h[2 * kNumClasses + 2 * cc + 1];
       if (big) {
-        st = fail(ctx, OPEN_E_UNSUPPORTED, "rank 64 with more than 32 observed entries in a row or column");
+        st = fail(ctx, OPEN_E_UNSUPPORTED,
+                  "rank 64 with 33 to 1023 observed entries in a row or column (dual form up to 32, split-K from 1024)");
         break;
       }
     }
     for (int s = 0; s < sweeps && !st; ++s) {
       if ((st = rowsolve_launch(ctx, V, n, k, row_ptr, col, val, lambda, weighted, list_r, cls_r, U, nullptr, m)))
         break;
+      if ((st = splitk_launch(ctx, V, n, k, col, val, lambda, weighted, list_r, cls_r, U, nullptr, m, nnz))) break;
       if (obj_hist &&
           (st = objective_dispatch(ctx, k, m, n, row_ptr, col, val, U, V, lambda, weighted, cp, obj_d + 2 * s)))
         break;
       if ((st = rowsolve_launch(ctx, U, (int)m, k, cp, ri, cv, lambda, weighted, list_c, cls_c, V, nullptr, n)))
         break;
+      if ((st = splitk_launch(ctx, U, (int)m, k, ri, cv, lambda, weighted, list_c, cls_c, V, nullptr, n, nnz))) break;
       if (obj_hist &&
           (st = objective_dispatch(ctx, k, m, n, row_ptr, col, val, U, V, lambda, weighted, cp, obj_d + 2 * s + 1)))
         break;

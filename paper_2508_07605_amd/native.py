@@ -349,17 +349,6 @@ class Surrogate:
                                              ctypes.byref(nf) if count else None))
         return U_out, (nf.value if count else None)
 
-    def tune_get(self, k):
-        """Chosen kernel variant per class group of rank k."""
-        ng = len(open_tune_info(k))
-        buf = (ctypes.c_int8 * ng)()
-        self.check(lib().open_tune_get(self.handle, k, buf, ng))
-        return list(buf)
-
-    def tune_set(self, k, choice):
-        buf = (ctypes.c_int8 * len(choice))(*choice)
-        self.check(lib().open_tune_set(self.handle, k, buf, len(choice)))
-
     def close(self):
         if getattr(self, "handle", None):
             lib().open_mlp_destroy(self.handle)

@@ -189,3 +189,40 @@ def test_autotune_result_and_cache(ctx, tmp_path):
         assert autotune.load(c2, 32, path) == got == c2.tune_get(32)
     finally:
         c2.close()
+
+
+@pytest.mark.parametrize("k", [8, 16, 32, 64])
+@pytest.mark.parametrize("weighted", [True, False])
+def test_split_k_long_rows(ctx, k, weighted):
+    # rows with at least 1024 observed entries take the split-K path (chunks of 1024 entries,
+    # partial Gram matrices reduced in chunk order); mixed with short rows of the other paths
+    r = np.random.default_rng(400 + k + int(weighted))
+    n = 3000
+    long_counts = r.integers(1024, n + 1, size=23)
+    long_counts[:3] = [1024, 2048, n]  # one chunk, exactly two chunks, the whole column set
+    short_max = 32 if k == 64 else 200
+    counts = np.concatenate([long_counts, r.integers(0, short_max + 1, size=200)])
+    r.shuffle(counts)
+    rp, col, val = csr_from_counts(r, counts, n)
+    V = (r.normal(size=(n, k)) * 0.3).astype(np.float32)
+    U, st = run_gpu(ctx, V, rp, col, val, 0.05, weighted)
+    ref, ref_st = oracle.ridge_rows(rp, col, val, V, 0.05, weighted)
+    assert np.array_equal(st, ref_st)
+    e = rel_err(U, ref)[counts > 0]
+    report("split-K k%d w%d" % (k, weighted), e)
+    assert e.max() <= TOL
+
+
+def test_split_k_statuses(ctx):
+    r = np.random.default_rng(77)
+    n, k = 2500, 32
+    counts = [1500, 1200, 1100, 1300]
+    rp, col, val = csr_from_counts(r, counts, n)
+    V = (r.normal(size=(n, k)) * 0.3).astype(np.float32)
+    val[rp[1] + 700] = np.nan    # row 1: non-finite value in its first chunk
+    col[rp[2] + 1050] = n + 5    # row 2: column index out of range in its second chunk
+    U, st = run_gpu(ctx, V, rp, col, val, 0.05)
+    assert st.tolist() == [0, 3, 5, 0]
+    assert (U[[1, 2]] == 0).all()
+    ref, _ = oracle.ridge_rows(rp[[0, 1]], col[rp[0]:rp[1]], val[rp[0]:rp[1]], V, 0.05, True)
+    assert rel_err(U[[0]], ref).max() <= TOL
