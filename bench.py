@@ -229,6 +229,8 @@ def main():
                     help="also run a 256 MiB device copy (reference kernel for HBM counter scaling)")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel variants")
+    ap.add_argument("--graph", action="store_true", help="time the pass as one HIP graph replay instead of "
+                                                          "kernel-by-kernel launches")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate (MLP + fallback) leg")
     ap.add_argument("--no-predict", action="store_true", help="skip the predict + selection leg")
     ap.add_argument("--no-fit", action="store_true", help="skip the ALS fit leg")
@@ -264,8 +266,13 @@ def main():
     dst = torch.empty(m, dtype=torch.int32, device=dev)
     ctx = native.Context(0)
 
-    def step():
+    def step_eager():
         native.open_foldin(ctx, dV, drp, dcol, dval, lam, True, U_out=dU, row_status=dst)
+
+    def step_graph():
+        native.open_foldin_graph(ctx, dV, drp, dcol, dval, lam, True, U_out=dU, row_status=dst)
+
+    step = step_graph if args.graph else step_eager
 
     if args.copy_calib:
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
@@ -302,9 +309,22 @@ def main():
     assert (st == 0).all(), "row status not ok: %s" % np.bincount(st)
 
     # live per-kernel timing (HIP events around each launch, on the library's stream)
+    # the other launch mode of the same pass
+    other = step_eager if args.graph else step_graph
+    for _ in range(args.warmup):
+        other()
+    torch.cuda.synchronize()
+    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev2.record()
+    for _ in range(args.steps):
+        other()
+    ev3.record()
+    torch.cuda.synchronize()
+    other_ms = ev2.elapsed_time(ev3) / args.steps
+    # per-kernel timing, kernel by kernel (a graph replay has no per-kernel events)
     ctx.profile(True)
     for _ in range(args.profile_steps):
-        step()
+        step_eager()
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
     counts = rows.counts()
@@ -343,6 +363,8 @@ def main():
                                % m, "rows": m, "settings": grid.n, "rank": k, "nnz": rows.nnz,
                    "parallelism": "single GPU", "kernel_variants": variants},
         "pass_tflops": round(pass_tflops, 3),
+        "launch": "one HIP graph replay per pass" if args.graph else "kernel by kernel",
+        ("eager_ms_per_step" if args.graph else "graph_ms_per_step"): other_ms,
         "roofline": roofline,
     }
 

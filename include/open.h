@@ -95,6 +95,18 @@ open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int
                         int32_t *row_status);
 
 /*
+ * Fold-in through a HIP graph: the same result as open_foldin (same kernels, same order).
+ * The first call with a given set of arguments runs eagerly and records the launch sequence
+ * into a graph held by the context; a later call with identical pointers, sizes, lambda,
+ * weighting and kernel-variant choice replays it with one hipGraphLaunch (the values behind
+ * the pointers may change between calls).  Other arguments re-record.  Only the sync-free
+ * fold-in can be recorded: rank 8, 16 or 32 and n < 1024 (else OPEN_E_UNSUPPORTED).
+ */
+open_status open_foldin_graph(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m,
+                              const int64_t *row_ptr, const int32_t *col, const float *val, float lambda,
+                              int32_t weighted, float *U_out, int32_t *row_status);
+
+/*
  * Kernel variants and autotuning (the fold-in's batched solves, Section III-B.2, run one
  * kernel per size class of |O_i|; each class group has up to 4 compiled configurations:
  * lanes per system, waves per block, waves per SIMD).  The choice is per context and rank
@@ -135,7 +147,12 @@ open_status open_csr_to_csc(open_ctx *ctx, int64_t m, int32_t n, const int64_t *
  * on entry and the fitted factors on return.  obj_hist, when not NULL, is a HOST array of
  * 2*sweeps doubles receiving the objective
  *     f = sum_O (r_ij - u_i.v_j)^2 + lambda (sum_i w_i |u_i|^2 + sum_j w^j |v_j|^2)
- * after every half-sweep; it makes the call synchronous.
+ * after every half-sweep; it makes the call synchronous.  Rows and columns with at least 1024
+ * observed entries are solved by the split-K path (chunked Gram matrices, reduced in chunk
+ * order); rank 64 supports up to 32 and from 1024 observed entries per row or column.
+ * Without obj_hist and with sweeps >= 2, the first sweep runs eagerly and the others replay
+ * it as one HIP graph (the same kernels in the same order).  The call returns after its
+ * temporary buffers are released, so it drains the stream.
  */
 open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64_t *row_ptr, const int32_t *col,
                      const float *val, float lambda, int32_t weighted, int32_t sweeps, float *U, float *V,

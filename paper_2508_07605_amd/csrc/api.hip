@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <functional>
 #include <new>
 #include <string>
 
@@ -15,6 +16,8 @@ namespace openk {
 
 open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out) {
   if (bytes == 0) bytes = 16;
+  if (ctx->ws_bytes[slot] < bytes && ctx->capturing)
+    return fail(ctx, OPEN_E_UNSUPPORTED, "workspace growth during graph capture");
   if (ctx->ws_bytes[slot] < bytes) {
     if (ctx->ws[slot]) {
       // the stream may still use the old buffer: drain before releasing it
@@ -36,6 +39,7 @@ open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out) {
 }
 
 open_status pinned_get(open_ctx *ctx, size_t bytes, void **out) {
+  if (ctx->capturing) return fail(ctx, OPEN_E_UNSUPPORTED, "host read-back during graph capture");
   if (ctx->host_pinned_bytes < bytes) {
     if (ctx->host_pinned) {
       OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -83,6 +87,34 @@ static open_status check_csr(open_ctx *ctx, int64_t m, const int64_t *row_ptr, c
   return OPEN_OK;
 }
 
+// Capture the launches of fn() on a private stream into a graph (nothing runs).
+open_status graph_capture(open_ctx *ctx, const std::function<open_status()> &fn, hipGraph_t *out) {
+  *out = nullptr;
+  if (!ctx->cap_stream) OPEN_HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = ctx->stream;
+  const bool prof = ctx->prof_on;
+  OPEN_HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  ctx->stream = ctx->cap_stream;
+  ctx->capturing = true;
+  ctx->prof_on = false;
+  open_status st = fn();
+  ctx->stream = user;
+  ctx->capturing = false;
+  ctx->prof_on = prof;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess || !g) {
+    (void)hipGetLastError();
+    return fail(ctx, OPEN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return OPEN_OK;
+}
+
 }  // namespace openk
 
 using namespace openk;
@@ -120,6 +152,9 @@ open_status open_destroy(open_ctx *ctx) {
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return OPEN_OK;
 }
@@ -227,6 +262,53 @@ open_status open_foldin(open_ctx *ctx, const float *F, int32_t n, int32_t k, int
   if ((st = rowsolve_launch(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m)))
     return st;
   if (nnz >= 0) return splitk_launch(ctx, F, n, k, col, val, lambda, weighted, list, cls, U_out, row_status, m, nnz);
+  return OPEN_OK;
+}
+
+open_status open_foldin_graph(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m, const int64_t *row_ptr,
+                              const int32_t *col, const float *val, float lambda, int32_t weighted, float *U_out,
+                              int32_t *row_status) {
+  if (!ctx) return OPEN_E_INVALID;
+  if (k == 64 || n >= kSplitMin)
+    return fail(ctx, OPEN_E_UNSUPPORTED, "graph replay needs rank 8, 16 or 32 and fewer than 1024 factor rows");
+  open_ctx::FoldinKey key;
+  memset(&key, 0, sizeof(key));
+  key.F = F;
+  key.n = n;
+  key.k = k;
+  key.m = m;
+  key.row_ptr = row_ptr;
+  key.col = col;
+  key.val = val;
+  key.lambda = lambda;
+  key.weighted = weighted;
+  key.U = U_out;
+  key.status = row_status;
+  if (rank_ok(k)) memcpy(key.tune, ctx->tune[rank_index(k)], sizeof(key.tune));
+  if (ctx->graph_exec && memcmp(&key, &ctx->gkey, sizeof(key)) == 0) {
+    OPEN_HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    return OPEN_OK;
+  }
+  // eager pass: validates the arguments, sizes the workspaces and produces this call's result
+  open_status st = open_foldin(ctx, F, n, k, m, row_ptr, col, val, lambda, weighted, U_out, row_status);
+  if (st || m == 0) return st;
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  hipGraph_t g;
+  st = graph_capture(ctx, [&]() { return open_foldin(ctx, F, n, k, m, row_ptr, col, val, lambda, weighted, U_out,
+                                               row_status); }, &g);
+  if (st) return st;
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    return fail(ctx, OPEN_E_DEVICE, "graph instantiation failed");
+  }
+  ctx->graph = g;
+  ctx->graph_exec = ex;
+  memcpy(&ctx->gkey, &key, sizeof(key));  // byte copy: the key is compared with memcmp
   return OPEN_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -117,6 +118,25 @@ struct open_ctx {
   size_t ws_bytes[WS_COUNT] = {};
   // chosen kernel variant of each size-class group, per rank (8, 16, 32, 64); 0 = default
   int8_t tune[4][16] = {};
+  // graph capture: while capturing, launches go to cap_stream and nothing may allocate or sync
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  // the fold-in graph of the last open_foldin_graph arguments
+  struct FoldinKey {
+    const float *F;
+    int n, k;
+    int64_t m;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const float *val;
+    float lambda;
+    int weighted;
+    float *U;
+    int32_t *status;
+    int8_t tune[16];
+  } gkey = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   void *host_pinned = nullptr;  // small pinned staging buffer for synchronous scalar results
   size_t host_pinned_bytes = 0;
   // optional per-kernel timing (HIP events around each launch)
@@ -193,6 +213,9 @@ open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const i
 open_status splitk_launch(open_ctx *ctx, const float *F, int nF, int k, const int32_t *idx, const float *val,
                           float lambda, int weighted, const RowRef *list, const int64_t *cls, float *X,
                           int32_t *status, int64_t m, int64_t nnz);
+// Record the launches of fn() into a HIP graph on the context's capture stream (nothing runs;
+// allocation and host read-back fail while capturing).
+open_status graph_capture(open_ctx *ctx, const std::function<open_status()> &fn, hipGraph_t *out);
 // Kernel variants: at most kMaxVariants per class group; rank_index maps 8/16/32/64 to 0..3.
 constexpr int kMaxVariants = 4;
 int rank_index(int k);

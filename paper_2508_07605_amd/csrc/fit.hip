@@ -452,6 +452,34 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
         break;
       }
     }
+    auto sweep = [&]() -> open_status {
+      open_status e;
+      if ((e = rowsolve_launch(ctx, V, n, k, row_ptr, col, val, lambda, weighted, list_r, cls_r, U, nullptr, m)))
+        return e;
+      if ((e = splitk_launch(ctx, V, n, k, col, val, lambda, weighted, list_r, cls_r, U, nullptr, m, nnz))) return e;
+      if ((e = rowsolve_launch(ctx, U, (int)m, k, cp, ri, cv, lambda, weighted, list_c, cls_c, V, nullptr, n)))
+        return e;
+      return splitk_launch(ctx, U, (int)m, k, ri, cv, lambda, weighted, list_c, cls_c, V, nullptr, n, nnz);
+    };
+    if (!obj_hist && sweeps >= 2 && !ctx->prof_on) {
+      // the first sweep runs eagerly (and sizes the workspaces); the others replay it as one graph
+      if ((st = sweep())) break;
+      hipGraph_t g = nullptr;
+      if ((st = graph_capture(ctx, sweep, &g))) break;
+      hipGraphExec_t ex = nullptr;
+      if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        st = fail(ctx, OPEN_E_DEVICE, "graph instantiation failed");
+        break;
+      }
+      for (int s = 1; s < sweeps && !st; ++s)
+        if (hipGraphLaunch(ex, ctx->stream) != hipSuccess) st = fail(ctx, OPEN_E_DEVICE, "graph launch failed");
+      (void)hipStreamSynchronize(ctx->stream);  // the graph is released below
+      (void)hipGraphExecDestroy(ex);
+      (void)hipGraphDestroy(g);
+      break;
+    }
     for (int s = 0; s < sweeps && !st; ++s) {
       if ((st = rowsolve_launch(ctx, V, n, k, row_ptr, col, val, lambda, weighted, list_r, cls_r, U, nullptr, m)))
         break;

@@ -33,6 +33,7 @@ SIGNATURES = {
     "open_profile": (_I32, [_P, _I32]),
     "open_profile_read": (_I32, [_P, _P, _P, _P, _I32, _I32]),
     "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
+    "open_foldin_graph": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_tune_info": (_I32, [_I32, _P, _P, _I32]),
     "open_tune_get": (_I32, [_P, _I32, _P, _I32]),
     "open_tune_set": (_I32, [_P, _I32, _P, _I32]),
@@ -169,6 +170,20 @@ def open_foldin(ctx, F, row_ptr, col, val, lam, weighted=True, U_out=None, row_s
                                 _dev(val, torch.float32, "val"), float(lam), int(bool(weighted)),
                                 _dev(U_out, torch.float32, "U_out", m * k),
                                 _dev(row_status, torch.int32, "row_status", m)))
+    return U_out
+
+
+def open_foldin_graph(ctx, F, row_ptr, col, val, lam, weighted=True, U_out=None, row_status=None):
+    """open_foldin recorded once into a HIP graph and replayed while the arguments repeat."""
+    n, k = F.shape
+    m = row_ptr.numel() - 1
+    if U_out is None:
+        U_out = torch.empty((m, k), dtype=torch.float32, device=F.device)
+    ctx.check(lib().open_foldin_graph(ctx.handle, _dev(F, torch.float32, "F"), n, k, m,
+                                      _dev(row_ptr, torch.int64, "row_ptr", m + 1), _dev(col, torch.int32, "col"),
+                                      _dev(val, torch.float32, "val"), float(lam), int(bool(weighted)),
+                                      _dev(U_out, torch.float32, "U_out", m * k),
+                                      _dev(row_status, torch.int32, "row_status", m)))
     return U_out
 
 

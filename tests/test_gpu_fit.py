@@ -123,3 +123,16 @@ def test_fit_config_shape(ctx):
     oe = np.abs(obj - objr).max() / objr.max()
     print("fit k32: UV^T %.3e  U %.3e  V %.3e  objective %.3e" % (pe, fro_rel(Ug, Ur), fro_rel(Vg, Vr), oe))
     assert pe <= 1e-4 and oe <= 1e-4
+
+
+def test_fit_graph_replay_matches_eager(ctx):
+    # without an objective history the sweeps after the first replay one recorded HIP graph;
+    # with it every launch is eager: the same kernels in the same order give identical factors
+    c, grid, rows = fit_rows("fit", m=6_000, seed=9)
+    U0, V0 = synth.init_factors(c["cfg_id"], rows.m, grid.n, c["k"], seed=9)
+    args = (dev(rows.row_ptr), dev(rows.col), dev(rows.val))
+    Ug, Vg = dev(U0), dev(V0)
+    native.open_fit(ctx, *args, Ug, Vg, c["lam"], 4, True, want_obj=False)
+    Ue, Ve = dev(U0), dev(V0)
+    native.open_fit(ctx, *args, Ue, Ve, c["lam"], 4, True, want_obj=True)
+    assert torch.equal(Ug, Ue) and torch.equal(Vg, Ve)

@@ -226,3 +226,41 @@ def test_split_k_statuses(ctx):
     assert (U[[1, 2]] == 0).all()
     ref, _ = oracle.ridge_rows(rp[[0, 1]], col[rp[0]:rp[1]], val[rp[0]:rp[1]], V, 0.05, True)
     assert rel_err(U[[0]], ref).max() <= TOL
+
+
+def test_foldin_graph_replays(ctx):
+    # record once, then replay with new values behind the same pointers, with eager work on
+    # the stream between replays; every replay equals the eager fold-in of the same inputs
+    grid = synth.grid_of("foldin")
+    V = synth.setting_factors(3, grid, 32, m_ref=1024)
+    a = synth.draw_rows(3, grid, 9001, ("uniform", 4, 24), seed=31)
+    dV, drp, dcol, dval = dev(V), dev(a.row_ptr), dev(a.col), dev(a.val)
+    U = torch.empty((a.m, 32), dtype=torch.float32, device="cuda")
+    st = torch.empty(a.m, dtype=torch.int32, device="cuda")
+    gen = torch.Generator(device="cpu").manual_seed(3)
+    for rep in range(4):
+        if rep:
+            dval.copy_(torch.rand(dval.numel(), generator=gen).mul_(0.6).add_(0.4).cuda())
+            dV.mul_(1.01)
+        native.open_foldin_graph(ctx, dV, drp, dcol, dval, 0.05, True, U_out=U, row_status=st)
+        other = native.open_foldin(ctx, dV, drp, dcol, dval, 0.05, True)  # eager work in between
+        torch.cuda.synchronize()
+        ref = native.open_foldin(ctx, dV, drp, dcol, dval, 0.05, True)
+        torch.cuda.synchronize()
+        assert torch.equal(U, ref) and torch.equal(other, ref), "replay %d" % rep
+        assert (st == 0).all()
+    # a different lambda records a new graph
+    native.open_foldin_graph(ctx, dV, drp, dcol, dval, 0.1, True, U_out=U)
+    torch.cuda.synchronize()
+    assert torch.equal(U, native.open_foldin(ctx, dV, drp, dcol, dval, 0.1, True))
+    # the result also matches the oracle
+    ref64, _ = oracle.ridge_rows(a.row_ptr, a.col, dval.cpu().numpy(), dV.cpu().numpy(), 0.1, True)
+    assert rel_err(U.cpu().numpy().astype(np.float64), ref64).max() <= TOL
+
+
+def test_foldin_graph_unsupported_shapes(ctx):
+    r = np.random.default_rng(1)
+    rp, col, val = csr_from_counts(r, [3, 4], 8)
+    V = (r.normal(size=(8, 64)) * 0.3).astype(np.float32)
+    with pytest.raises(native.OpenError):
+        native.open_foldin_graph(ctx, dev(V), dev(rp), dev(col), dev(val), 0.05)
