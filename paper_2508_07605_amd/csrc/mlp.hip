@@ -32,9 +32,23 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26 (absolute
+// error below 1.5e-7, under the float32 rounding of the activations):
+//   erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x),  x >= 0
+// and erf(-x) = -erf(x).  One reciprocal and one exponential instead of the library's erff.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = __builtin_fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.0f));
+  float q = __builtin_fmaf(t, 1.061405429f, -1.453152027f);
+  q = __builtin_fmaf(t, q, 1.421413741f);
+  q = __builtin_fmaf(t, q, -0.284496736f);
+  q = __builtin_fmaf(t, q, 0.254829592f);
+  const float e = __expf(-ax * ax);
+  return __builtin_copysignf(__builtin_fmaf(-t * q, e, 1.0f), x);
+}
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 // ---------------------------------------------------------------- bfloat16 weight copies
@@ -313,6 +327,201 @@ __global__ void k_count_u8(int64_t m, const uint8_t *__restrict__ f, int64_t *__
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------- fused inference
+// Surrogate fold-in of a tile of kIR rows per block iteration (persistent grid), the network
+// and the fallback test in one kernel: sparse first layer (each wavefront 16 rows, lane l
+// hidden units 4l..4l+3) -> GELU -> bfloat16 tile in LDS -> second layer on BF16 MFMA with
+// this wavefront's 64 columns of W2 held in registers for the whole kernel -> GELU -> LDS
+// (over the first tile) -> third layer on MFMA -> u to global and LDS -> observed-entry RMS
+// residual against the setting factors (four lanes per row) -> fallback flag.  Every
+// arithmetic step matches the batched forward (same products, same order, same roundings).
+constexpr int kIR = 64;       // rows per tile
+constexpr int kHP = 256 + 8;  // LDS pitch of an activation row (bf16)
+
+template <int K>
+__global__ __launch_bounds__(256, 2) void k_mlp_infer(int64_t m, const int64_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                      int n, const uint16_t *__restrict__ W1T,
+                                                      const float *__restrict__ b1, const float *__restrict__ W2,
+                                                      const float *__restrict__ b2, const float *__restrict__ W3,
+                                                      const float *__restrict__ b3, const float *__restrict__ F,
+                                                      float tau, float *__restrict__ U, float *__restrict__ rho,
+                                                      uint8_t *__restrict__ flag) {
+  constexpr int CB3 = (K + 31) / 32;  // 32-column blocks of the output layer
+  __shared__ __attribute__((aligned(16))) uint16_t Hs[kIR * kHP];
+  __shared__ float Us[kIR * K];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i32 = lane & 31, g = lane >> 5;
+  // B operands of the second layer: W2[64w + 32cb + i32][16ks + 8g .. +8] as bfloat16
+  uint4 w2r[2][16];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const float *src = W2 + (int64_t)(64 * w + 32 * cb + i32) * 256 + 16 * ks + 8 * g;
+      uint32_t pk[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pk[e] = (uint32_t)f2bf(src[2 * e]) | ((uint32_t)f2bf(src[2 * e + 1]) << 16);
+      w2r[cb][ks] = uint4{pk[0], pk[1], pk[2], pk[3]};
+    }
+  const float b2c[2] = {b2[64 * w + i32], b2[64 * w + 32 + i32]};
+  const int64_t ntiles = (m + kIR - 1) / kIR;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * kIR;
+    // ---- first layer (sparse), GELU, bfloat16 into LDS.  A row's entries are fetched 64 at
+    // a time, one per lane, then taken in order, eight weight gathers in flight at once.
+    for (int q = 0; q < 16; ++q) {
+      const int lr = 16 * w + q;
+      const int64_t row = r0 + lr;
+      f4 z = *reinterpret_cast<const f4 *>(b1 + 4 * lane);
+      const int64_t t0 = row < m ? ptr[row] : 0, t1 = row < m ? ptr[row + 1] : 0;
+      for (int64_t base = t0; base < t1; base += 64) {
+        const int nb = (int)(t1 - base < 64 ? t1 - base : 64);
+        const int jl = lane < nb ? col[base + lane] : -1;
+        const float rl = lane < nb ? val[base + lane] : 0.f;
+        for (int u0 = 0; u0 < nb; u0 += 8) {
+          uint2 wa[8], wm[8];
+          int jj[8];
+          float rr[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int t = u0 + e < nb ? u0 + e : nb - 1;
+            jj[e] = __builtin_amdgcn_readlane(jl, t);
+            rr[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, rl), t));
+            const int js = (jj[e] >= 0 && jj[e] < n) ? jj[e] : 0;
+            wa[e] = *reinterpret_cast<const uint2 *>(W1T + (int64_t)js * 256 + 4 * lane);
+            wm[e] = *reinterpret_cast<const uint2 *>(W1T + (int64_t)(n + js) * 256 + 4 * lane);
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if (u0 + e < nb && jj[e] >= 0 && jj[e] < n) {  // wave-uniform
+              const float r = rr[e];
+              z[0] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].x & 0xffff)), bf2f((uint16_t)(wm[e].x & 0xffff)));
+              z[1] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].x >> 16)), bf2f((uint16_t)(wm[e].x >> 16)));
+              z[2] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].y & 0xffff)), bf2f((uint16_t)(wm[e].y & 0xffff)));
+              z[3] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].y >> 16)), bf2f((uint16_t)(wm[e].y >> 16)));
+            }
+          }
+        }
+      }
+      const uint32_t lo = (uint32_t)f2bf(gelu(z[0])) | ((uint32_t)f2bf(gelu(z[1])) << 16);
+      const uint32_t hi = (uint32_t)f2bf(gelu(z[2])) | ((uint32_t)f2bf(gelu(z[3])) << 16);
+      *reinterpret_cast<uint2 *>(Hs + lr * kHP + 4 * lane) = uint2{lo, hi};
+    }
+    __syncthreads();
+    // ---- second layer: this wavefront's 64 output columns for all kIR rows
+    f16 acc[2][2] = {};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32) * kHP + 16 * ks + 8 * g);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                               __builtin_bit_cast(bf16x8, w2r[cb][ks]), acc[rb][cb],
+                                                               0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wavefront has read the first layer's tile
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int rr = 32 * rb + 8 * (v / 4) + 4 * g + (v % 4);
+          Hs[rr * kHP + 64 * w + 32 * cb + i32] = f2bf(gelu(acc[rb][cb][v] + b2c[cb]));
+        }
+    __syncthreads();
+    // ---- third layer: tiles (row block, 32 outputs) on the first 2 CB3 wavefronts
+    if (w < 2 * CB3) {
+      const int rb = w & 1, cb = w >> 1;
+      const int oc = 32 * cb + i32;  // output column supplied / received by this lane
+      f16 acc3 = {};
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32) * kHP + 16 * ks + 8 * g);
+        uint32_t pk[4] = {0, 0, 0, 0};
+        if (oc < K) {
+          const float *src = W3 + (int64_t)oc * 256 + 16 * ks + 8 * g;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pk[e] = (uint32_t)f2bf(src[2 * e]) | ((uint32_t)f2bf(src[2 * e + 1]) << 16);
+        }
+        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                      __builtin_bit_cast(bf16x8, uint4{pk[0], pk[1], pk[2], pk[3]}),
+                                                      acc3, 0, 0, 0);
+      }
+      if (oc < K) {
+        const float bias = b3[oc];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int rr = 32 * rb + 8 * (v / 4) + 4 * g + (v % 4);
+          const float x = acc3[v] + bias;
+          Us[rr * K + oc] = x;
+          if (r0 + rr < m) U[(r0 + rr) * K + oc] = x;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- observed-entry RMS residual: four lanes per row, K/4 dimensions each
+    {
+      constexpr int KQ = K / 4;
+      const int lr = 16 * w + (lane >> 2), pq = lane & 3;
+      const int64_t row = r0 + lr;
+      int64_t t0 = 0, t1 = 0;
+      if (row < m) {
+        t0 = ptr[row];
+        t1 = ptr[row + 1];
+      }
+      const int cnt = (int)(t1 - t0);
+      int cmax = cnt;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(cmax, off, 64);
+        cmax = o > cmax ? o : cmax;
+      }
+      float ssq = 0.f;
+      for (int t0b = 0; t0b < cmax; t0b += 4) {
+        // four entries in flight: indices and values, then the factor rows, then the dots
+        int jv[4];
+        float rv[4];
+        const float *fv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int t = t0b + e;
+          const bool in = t < cnt;
+          jv[e] = in ? col[t0 + t] : -1;
+          rv[e] = in ? val[t0 + t] : 0.f;
+          const bool ok = jv[e] >= 0 && jv[e] < n;
+          fv[e] = F + (int64_t)(ok ? jv[e] : 0) * K + pq * KQ;
+        }
+        float fx[4][KQ];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int a = 0; a < KQ; ++a) fx[e][a] = fv[e][a];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float d = 0.f;
+#pragma unroll
+          for (int a = 0; a < KQ; ++a) d = __builtin_fmaf(Us[lr * K + pq * KQ + a], fx[e][a], d);
+          d += __shfl_xor(d, 1, 64);
+          d += __shfl_xor(d, 2, 64);
+          const float er = rv[e] - d;
+          if (jv[e] >= 0 && jv[e] < n) ssq = __builtin_fmaf(er, er, ssq);
+        }
+      }
+      if (pq == 0 && row < m) {
+        const float rh = cnt > 0 ? sqrtf(ssq / (float)cnt) : 0.f;
+        rho[row] = rh;
+        flag[row] = (cnt > 0) && !(rh <= tau);
+      }
+    }
+    __syncthreads();  // the tile buffers are reused
+  }
 }
 
 }  // namespace openk
@@ -660,11 +869,30 @@ open_status open_mlp_foldin(open_mlp *p, const float *F, int64_t m, const int64_
     }
     p->icap = m;
   }
-  if ((st = open_mlp_forward(p, m, row_ptr, col, val, U_out))) return st;
   float *r = rho ? rho : p->rho;
   uint8_t *f = used_fallback ? used_fallback : p->flag;
-  if ((st = open_residual(ctx, m, p->n, p->k, row_ptr, col, val, U_out, F, r))) return st;
-  OPEN_LAUNCH(ctx, "mlp_fallback_flag", k_fallback_flag, dim3(1024), dim3(256), 0, m, row_ptr, r, tau, f);
+  // network, residual and fallback flag in one persistent kernel
+  const int64_t tiles = (m + kIR - 1) / kIR;
+  const unsigned grid = (unsigned)(tiles < (int64_t)ctx->num_cu * 2 ? tiles : (int64_t)ctx->num_cu * 2);
+  const float *W = p->w;
+  switch (p->k) {
+    case 8:
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<8>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
+                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      break;
+    case 16:
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<16>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
+                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      break;
+    case 32:
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<32>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
+                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      break;
+    default:
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<64>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
+                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      break;
+  }
   // re-solve the flagged rows with the ridge fold-in (only they are bucketed)
   RowRef *list;
   int64_t *cls;
