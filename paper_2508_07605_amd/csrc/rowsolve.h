@@ -315,9 +315,11 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
         lc[m] = go * (-s);
         bm[m] = __builtin_fmaf(go, ty, bm[m]);
       });
+      // the pivot's own tile column is finished when p is its last column (lc = 0 there)
+      constexpr int m0 = pp == P - 1 ? mp + 1 : mp;
       sfor<p + 1, D>([&](auto R) {
         constexpr int r = decltype(R)::value;
-        sfor<mp, (r / P + 1 < M ? r / P + 1 : M)>([&](auto Mm) {
+        sfor<m0, (r / P + 1 < M ? r / P + 1 : M)>([&](auto Mm) {
           constexpr int m = decltype(Mm)::value;
           st[m][r - P * m] = __builtin_fmaf(g[r], lc[m], st[m][r - P * m]);
         });
@@ -346,6 +348,8 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
     if constexpr (DUAL) {
       const int j = ixs[sme * E + p];
       sfor<0, KO / 4>([&](auto c) { u[c] += xp * Fr.row4(j, pi * KO + 4 * c); });
+      // keep the factor-row reads of later pivots from being hoisted here (register pressure)
+      if constexpr (D >= 20) __builtin_amdgcn_sched_barrier(0);
     } else {
       if constexpr (P == 1)
         bm[mp] = xo;
