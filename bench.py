@@ -200,19 +200,31 @@ def fit_leg(args, ctx, log):
     native.open_fit(ctx, drp, dcol, dval, dU, dV, lam, 1)  # warm-up sweep (workspaces, code)
     torch.cuda.synchronize()
     S = args.fit_sweeps
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    native.open_fit(ctx, drp, dcol, dval, dU, dV, lam, S)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / S
+
+    def timed_fit(sweeps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        native.open_fit(ctx, drp, dcol, dval, dU, dV, lam, sweeps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    t1 = timed_fit(1)
+    tS = timed_fit(S + 1)
+    ms = (tS - t1) / S          # one more sweep, setup excluded
+    setup_ms = t1 - ms          # column view, bucketings, temporaries of one call
+    ctx.profile(True)
+    native.open_fit(ctx, drp, dcol, dval, dU, dV, lam, 1)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    log("fit: kernels (one call, one sweep) %s" % json.dumps({n: round(t, 4) for n, (t, c) in prof.items()}))
     obj = native.open_objective(ctx, drp, dcol, dval, dU, dV, lam)
     ccount = np.bincount(rows.col, minlength=grid.n)
     flops = float(row_flops(rows.counts(), k).sum() + row_flops(ccount, k).sum())
     tf = flops / (ms * 1e-3) / 1e12
     return {"workload": "ALS-WR fit: %d apps x %d settings, Zipf(1.2) counts on [3, 480], %d nnz, rank %d, "
                         "weighted lambda %g" % (rows.m, grid.n, rows.nnz, k, lam),
-            "ms_per_sweep": ms, "sweeps_timed": S, "objective_after": obj,
+            "ms_per_sweep": ms, "setup_ms_per_call": setup_ms, "sweeps_timed": S, "objective_after": obj,
             "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops}}
 

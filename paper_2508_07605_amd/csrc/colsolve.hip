@@ -17,6 +17,7 @@ namespace openk {
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int kSplitChunk = 1024;
+constexpr int kXcds = 8;  // accelerator complex dies of the MI355X, each with its own L2
 constexpr int kPrefixThreads = 1024;
 
 // MFMA geometry per rank: tile TK (16: v_mfma_f32_16x16x4f32, 32: v_mfma_f32_32x32x2f32),
@@ -65,6 +66,20 @@ __global__ __launch_bounds__(kPrefixThreads) void k_split_prefix(const RowRef *_
     run += (list[s0 + i].cnt + kSplitChunk - 1) / kSplitChunk;
   }
   if (threadIdx.x == kPrefixThreads - 1) chunk_start[cnt] = part[kPrefixThreads - 1];
+  // largest chunk count of a row, for the chunk-major visiting order of k_split_gram
+  __shared__ int64_t mx[kPrefixThreads];
+  int64_t m1 = 0;
+  for (int64_t i = b0; i < b1; ++i) {
+    const int64_t c = (list[s0 + i].cnt + kSplitChunk - 1) / kSplitChunk;
+    m1 = c > m1 ? c : m1;
+  }
+  mx[threadIdx.x] = m1;
+  __syncthreads();
+  for (int off = kPrefixThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off && mx[threadIdx.x + off] > mx[threadIdx.x]) mx[threadIdx.x] = mx[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) chunk_start[cnt + 1] = mx[0];
 }
 
 // Partial Gram and rhs of chunks g = wave, wave + waves, ... (persistent).  Lane l supplies
@@ -76,68 +91,114 @@ __global__ __launch_bounds__(256) void k_split_gram(const float *__restrict__ Uf
                                                     const int64_t *__restrict__ chunk_start, int nF,
                                                     float *__restrict__ part, int32_t *__restrict__ cflag) {
   using G = SplitGeo<K>;
-  constexpr int TK = G::TK, OBS = G::OBS, UNR = 8;
+  constexpr int TK = G::TK, OBS = G::OBS, UNR = 16;
+  // per wavefront: the chunk's indices and values, staged once with coalesced loads
+  __shared__ int jl_all[4][kSplitChunk];
+  __shared__ float rl_all[4][kSplitChunk];
+  int *jl = jl_all[threadIdx.x >> 6];
+  float *rl = rl_all[threadIdx.x >> 6];
   const int64_t s0 = cls[2 * kSplitClass], cnt = cls[2 * kSplitClass + 1];
   if (cnt == 0) return;
-  const int64_t total = chunk_start[cnt];
+  const int64_t cmax = chunk_start[cnt + 1];
+  const __amdgpu_buffer_rsrc_t urs = make_rsrc(Uf, (uint64_t)nF * K * sizeof(float));
   const int lane = threadIdx.x & 63;
   const int d = lane % TK, o = lane / TK;  // dimension and observation slot of this lane
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < total; g += nw) {
-    // column of chunk g: the last i with chunk_start[i] <= g
-    int64_t lo = 0, hi = cnt - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (chunk_start[mid] <= g) lo = mid; else hi = mid - 1;
-    }
+  // Visiting order.  Virtual index v = c * cnt + row runs chunk position-major, so wavefronts
+  // running together take the same chunk position of many rows, whose gathered factor rows
+  // then come from a narrow index range (the column view keeps entries sorted by row).
+  // Workgroups are dealt to the 8 XCDs round-robin: each XCD walks its own slabs of
+  // consecutive v, so the range it gathers from stays within its L2.
+  const int64_t total_v = cmax * cnt;
+  const bool xcd_order = gridDim.x % kXcds == 0;
+  const int64_t slab = xcd_order ? (int64_t)(gridDim.x / kXcds) * (blockDim.x >> 6) : nw;
+  const int64_t wx = xcd_order ? (int64_t)(blockIdx.x / kXcds) * (blockDim.x >> 6) + (threadIdx.x >> 6)
+                               : (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t first = xcd_order ? blockIdx.x % kXcds : 0, stride = xcd_order ? kXcds : 1;
+  for (int64_t sl = first; sl * slab < total_v; sl += stride) {
+    const int64_t v = sl * slab + wx;
+    if (v >= total_v) continue;
+    const int64_t lo = v % cnt, c = v / cnt;
+    const int64_t nch = chunk_start[lo + 1] - chunk_start[lo];
+    if (c >= nch) continue;  // this row has fewer chunks (wave-uniform)
+    const int64_t g = chunk_start[lo] + c;
     const RowRef rr = list[s0 + lo];
-    const int64_t c0 = (g - chunk_start[lo]) * kSplitChunk;
+    const int64_t c0 = c * kSplitChunk;
     const int64_t beg = rr.beg + c0;
     const int len = (int)((int64_t)rr.cnt - c0 < kSplitChunk ? (int64_t)rr.cnt - c0 : kSplitChunk);
-    f16v acc[G::NB];
+    // two accumulator sets (even and odd MFMA steps) so consecutive MFMAs do not depend on
+    // each other; summed once at the end
+    f16v acc[G::NB], acc2[G::NB];
     float bl = 0.f, bh = 0.f;
-    for (int b = 0; b < G::NB; ++b) acc[b] = f16v{};
-    f4 acc16 = {0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < G::NB; ++b) acc[b] = acc2[b] = f16v{};
+    f4 acc16 = {0.f, 0.f, 0.f, 0.f}, acc16b = {0.f, 0.f, 0.f, 0.f};
     int flags = 0;  // 1: non-finite value, 2: index outside [0, nF)
-    for (int t0 = 0; t0 < len; t0 += OBS * UNR) {
-      float ul[UNR], uh[UNR], rv[UNR];
+    // software pipeline: the operands of batch t + 1 load while batch t feeds the MFMAs
+    // stage: entry t of the chunk -> (jl[t], rl[t]); rejected or absent entries get j = -1
+    __builtin_amdgcn_wave_barrier();  // the previous chunk's reads are done
+#pragma unroll
+    for (int i = 0; i < kSplitChunk / 64; ++i) {
+      const int t = i * 64 + lane;
+      const bool in = t < len;
+      const int j = in ? ri[beg + t] : -1;
+      const float r = in ? cv[beg + t] : 0.f;
+      const bool jok = j >= 0 && j < nF;
+      if (in && !jok) flags |= 2;
+      if (in && !__builtin_isfinite(r)) flags |= 1;
+      jl[t] = jok ? j : -1;
+      rl[t] = r;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float ul[UNR], uh[UNR], rv[UNR];
+    // factor rows through a bounds-checked buffer resource: the row index -1 of absent or
+    // rejected entries reads zeros, so no per-element tests remain
+    auto load = [&](int t0) {
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int t = t0 + u * OBS + o;
-        const bool in = t < len;
-        const int64_t e = beg + (in ? t : 0);
-        const int j = ri[e];
-        const float r = cv[e];
-        const bool jok = j >= 0 && j < nF;
-        if (in && !jok) flags |= 2;
-        if (in && !__builtin_isfinite(r)) flags |= 1;
-        const bool ok = in && jok;
-        const float *urow = Uf + (int64_t)(jok ? j : 0) * K;
-        const float x = urow[d < K ? d : 0];  // in range for any lane; zeroed below
-        ul[u] = (ok && d < K) ? x : 0.f;
-        if constexpr (K == 64) {
-          const float xh = urow[32 + d];
-          uh[u] = ok ? xh : 0.f;
-        } else {
+        const int t = t0 + u * OBS + o;  // < kSplitChunk; entries past len were staged as -1
+        const int j = jl[t];
+        rv[u] = rl[t];
+        const uint32_t off = (uint32_t)(j * K + d) * 4u;
+        ul[u] = (K >= TK || d < K) ? bload_f32(urs, d < K ? off : 0xffffffffu) : 0.f;
+        if constexpr (K == 64)
+          uh[u] = bload_f32(urs, off + 128u);
+        else
           uh[u] = 0.f;
-        }
-        rv[u] = ok ? r : 0.f;
       }
+    };
+    load(0);
+    for (int t0 = 0; t0 < len; t0 += OBS * UNR) {
+      float cl[UNR], ch[UNR], cr[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
+        cl[u] = ul[u];
+        ch[u] = uh[u];
+        cr[u] = rv[u];
+      }
+      if (t0 + OBS * UNR < len) load(t0 + OBS * UNR);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        f16v *A = (u & 1) ? acc2 : acc;
         if constexpr (TK == 16) {
-          acc16 = __builtin_amdgcn_mfma_f32_16x16x4f32(ul[u], ul[u], acc16, 0, 0, 0);
+          if (u & 1)
+            acc16b = __builtin_amdgcn_mfma_f32_16x16x4f32(cl[u], cl[u], acc16b, 0, 0, 0);
+          else
+            acc16 = __builtin_amdgcn_mfma_f32_16x16x4f32(cl[u], cl[u], acc16, 0, 0, 0);
         } else {
-          acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ul[u], ul[u], acc[0], 0, 0, 0);
+          A[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(cl[u], cl[u], A[0], 0, 0, 0);
           if constexpr (K == 64) {
-            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(uh[u], ul[u], acc[1], 0, 0, 0);  // rows 32.., cols ..31
-            acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(uh[u], uh[u], acc[2], 0, 0, 0);
+            A[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ch[u], cl[u], A[1], 0, 0, 0);  // rows 32.., cols ..31
+            A[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(ch[u], ch[u], A[2], 0, 0, 0);
           }
         }
-        bl = __builtin_fmaf(rv[u], ul[u], bl);
-        if constexpr (K == 64) bh = __builtin_fmaf(rv[u], uh[u], bh);
+        bl = __builtin_fmaf(cr[u], cl[u], bl);
+        if constexpr (K == 64) bh = __builtin_fmaf(cr[u], ch[u], bh);
       }
     }
+    for (int b = 0; b < G::NB; ++b) acc[b] += acc2[b];
+    acc16 += acc16b;
     float *dst = part + g * G::PST;
     if constexpr (TK == 16) {
       for (int v = 0; v < 4; ++v) dst[v * 64 + lane] = acc16[v];
@@ -285,7 +346,8 @@ open_status splitk_launch(open_ctx *ctx, const float *F, int nF, int k, const in
   const int64_t max_chunks = nnz / kSplitChunk + max_rows + 1;
   void *cs = nullptr, *pt = nullptr, *cf = nullptr;
   open_status st;
-  if ((st = ws_get(ctx, open_ctx::WS_SPLIT_START, sizeof(int64_t) * (size_t)(max_rows + 1), &cs))) return st;
+  // chunk_start: one entry per long row, the total, and the largest chunk count
+  if ((st = ws_get(ctx, open_ctx::WS_SPLIT_START, sizeof(int64_t) * (size_t)(max_rows + 2), &cs))) return st;
   if ((st = ws_get(ctx, open_ctx::WS_SPLIT_PART, sizeof(float) * (size_t)max_chunks * split_part_floats(k), &pt)))
     return st;
   if ((st = ws_get(ctx, open_ctx::WS_SPLIT_FLAG, sizeof(int32_t) * (size_t)max_chunks, &cf))) return st;

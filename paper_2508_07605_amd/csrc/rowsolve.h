@@ -187,31 +187,45 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
       const int64_t qbeg = (int64_t)(uint32_t)__shfl((int)(mbeg & 0xffffffff), qsrc, 64) |
                            ((int64_t)__shfl((int)(mbeg >> 32), qsrc, 64) << 32);
       const int tmax = wave_max_i(cnt);
-      int jn = 0;
-      float rn = 0.f;
-      if (tmax > 0) {
-        jn = idx[cnt > 0 ? qbeg : 0];
-        rn = val[cnt > 0 ? qbeg : 0];
-      }
-      for (int t = 0; t < tmax; ++t) {
-        int j = jn;
-        const float r0 = rn;
-        if (t + 1 < tmax) {
-          const int64_t e = t + 1 < cnt ? qbeg + t + 1 : (cnt > 0 ? qbeg : 0);
-          jn = idx[e];
-          rn = val[e];
-        }
-        const bool ok = t < cnt;
-        if (ok && (j < 0 || j >= n)) pflags |= 2;
-        if (ok && !__builtin_isfinite(r0)) pflags |= 1;
-        j = (ok && j >= 0 && j < n) ? j : -1;
-        const float r = j >= 0 ? r0 : 0.f;
-        float a[N];
-        sfor<0, N>([&](auto J) { a[J] = Fr.row1(j, 4 * J + qi); });
-        sfor<0, N>([&](auto I) {
-          sfor<0, I + 1>([&](auto J) { acc[tri(I, J)] = mfma4x4(a[I], a[J], acc[tri(I, J)]); });
+      // indices and values PD entries ahead of the contraction
+      constexpr int PD = 4;
+      int jn[PD];
+      float rn[PD];
+      auto fetch = [&](int t0) {
+        sfor<0, PD>([&](auto E) {
+          const int t = t0 + (int)E;
+          const int64_t e = t < cnt ? qbeg + t : (cnt > 0 ? qbeg : 0);
+          jn[E] = idx[e];
+          rn[E] = val[e];
         });
-        sfor<0, N>([&](auto J) { pb[J] = __builtin_fmaf(r, a[J], pb[J]); });
+      };
+      if (tmax > 0) fetch(0);
+      for (int t0 = 0; t0 < tmax; t0 += PD) {
+        int jc[PD];
+        float rc[PD];
+        sfor<0, PD>([&](auto E) {
+          jc[E] = jn[E];
+          rc[E] = rn[E];
+        });
+        if (t0 + PD < tmax) fetch(t0 + PD);
+        sfor<0, PD>([&](auto E) {
+          const int t = t0 + (int)E;
+          if (t < tmax) {  // wave-uniform
+            const bool ok = t < cnt;
+            int j = jc[E];
+            const float r0 = rc[E];
+            if (ok && (j < 0 || j >= n)) pflags |= 2;
+            if (ok && !__builtin_isfinite(r0)) pflags |= 1;
+            j = (ok && j >= 0 && j < n) ? j : -1;
+            const float r = j >= 0 ? r0 : 0.f;
+            float a[N];
+            sfor<0, N>([&](auto J) { a[J] = Fr.row1(j, 4 * J + qi); });
+            sfor<0, N>([&](auto I) {
+              sfor<0, I + 1>([&](auto J) { acc[tri(I, J)] = mfma4x4(a[I], a[J], acc[tri(I, J)]); });
+            });
+            sfor<0, N>([&](auto J) { pb[J] = __builtin_fmaf(r, a[J], pb[J]); });
+          }
+        });
       }
     }
     // ridge term (unit diagonal on padded rows of a dual system)
