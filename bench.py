@@ -20,6 +20,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
 
@@ -52,6 +53,28 @@ def kernel_of_counts(n, k):
     out = names[np.minimum(d, 32)]
     out[n > dmax] = "ridge_k%d_primal" % k
     return out
+
+
+def recorded_traffic(kernel, choice):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
+    the summary covers another kernel or variant, or the kernel's sources changed since."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "ridge_foldin_1M_k32.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+    if not rec or rec.get("kernel") != kernel or rec.get("choice") != choice:
+        return None
+    h = hashlib.sha1()
+    for f in rec["sources"]:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["sources_sha1"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def surrogate_leg(args, ctx, dV, drp, dcol, dval, m, steps, warmup, log):
@@ -356,7 +379,8 @@ def main():
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roofline = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": recorded_traffic(dom, variants.get(dom)),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": dom, "kernel_ms": round(dom_ms, 4), "kernel_rows": dom_rows,
         "algorithmic_flops": dom_flops, "algorithmic_bytes": dom_bytes,
         "hbm_gbs": round(dom_bytes / (dom_ms * 1e-3) / 1e9, 1),
