@@ -159,6 +159,9 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
     const int cnt = __shfl(my_cnt, qsrc, 64);
     f4 acc[T];
     sfor<0, T>([&](auto t) { acc[t] = f4{0.f, 0.f, 0.f, 0.f}; });
+    // the MFMA phase issues at raised priority, so a wave in its Gram keeps the matrix pipe
+    // fed while the SIMD's other waves run their (VALU-bound) eliminations in the gaps
+    __builtin_amdgcn_s_setprio(1);
     if constexpr (DUAL) {
       int oi[N];
       sfor<0, N>([&](auto J) { oi[J] = ixs[qs * E + 4 * J + qi]; });
@@ -228,6 +231,7 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
         });
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     // ridge term (unit diagonal on padded rows of a dual system)
     const float reg = lambda * (weighted ? (float)cnt : 1.0f);
     sfor<0, N>([&](auto J) {
