@@ -200,6 +200,39 @@ def predict_leg(ctx, steps, warmup, log):
                          "algorithmic_bytes": byts, "hbm_gbs": round(byts / (ms * 1e-3) / 1e9, 1)}}
 
 
+def phase_leg(ctx, steps, warmup, log):
+    """Algorithm 1 (phase-transition detection) over 65,536 GPU power traces of 3000 readings
+    (10 min at 0.2 s): traces per second and HBM bytes actually needed (4 B per reading up to
+    each report, all readings of traces without one)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    T, L = 65536, 3000
+    t0 = time.time()
+    P = torch.from_numpy(synth.power_traces(7, T, L, seed=0)).cuda()
+    log("phase: %d traces x %d readings in %.1f s" % (T, L, time.time() - t0))
+    out = torch.empty(T, dtype=torch.int64, device=P.device)
+    for _ in range(warmup):
+        native.open_phase_detect(ctx, P, 60.0, 25, first_index=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        native.open_phase_detect(ctx, P, 60.0, 25, first_index=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    f = out.cpu().numpy()
+    byts = float(np.where(f >= 0, f + 1, L).sum() * 4)
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": "Alg. 1 phase detection: %d power traces x %d readings, window 25, 60 W" % (T, L),
+            "traces_per_s": T / (ms * 1e-3), "ms_per_step": ms, "detected_fraction": float((f >= 0).mean()),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": byts}}
+
+
 def fit_leg(args, ctx, log):
     """ALS-WR fit on 200k apps x 480 settings, truncated Zipf(1.2) observed counts on [3, 480]
     (12.7M observed entries), rank 32, weighted lambda 0.05: time per sweep (rows, then
@@ -269,6 +302,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate (MLP + fallback) leg")
     ap.add_argument("--no-predict", action="store_true", help="skip the predict + selection leg")
     ap.add_argument("--no-fit", action="store_true", help="skip the ALS fit leg")
+    ap.add_argument("--no-phase", action="store_true", help="skip the Alg. 1 phase-detection leg")
     ap.add_argument("--fit-sweeps", type=int, default=3, help="timed ALS sweeps in the fit leg")
     ap.add_argument("--surrogate-epochs", type=float, default=2.0,
                     help="training epochs over the 2M ALS fold-in targets (batch 4096, Adam 1e-3)")
@@ -409,6 +443,10 @@ def main():
         out["predict_select"] = predict_leg(ctx, args.steps, args.warmup, log)
         log("predict+select %.3e rows/s, %.1f TFLOP/s" % (out["predict_select"]["rows_per_s"],
                                                           out["predict_select"]["roofline"]["achieved"]))
+    if not args.no_phase:
+        out["phase_detect"] = phase_leg(ctx, args.steps, args.warmup, log)
+        log("phase detection %.3e traces/s, %.0f GB/s" % (out["phase_detect"]["traces_per_s"],
+                                                           out["phase_detect"]["roofline"]["achieved"]))
     if not args.no_fit:
         out["fit"] = fit_leg(args, ctx, log)
         log("fit %.3f ms/sweep, %.1f TFLOP/s" % (out["fit"]["ms_per_sweep"], out["fit"]["roofline"]["achieved"]))

@@ -107,6 +107,19 @@ open_status open_foldin_graph(open_ctx *ctx, const float *F, int32_t n, int32_t 
                               int32_t weighted, float *U_out, int32_t *row_status);
 
 /*
+ * Phase-transition detection (Algorithm 1, Section III-B.2) for T power traces at once.
+ * Trace t is power[t*ld .. t*ld + L) (device float32, GPU power readings in W at a fixed
+ * sampling interval).  first_index[t] (device int64) receives the 0-based index of the
+ * reading at which the last n_window readings are all >= threshold (the paper: 0.2 s
+ * sampling, 5 s window -> n_window = 25, threshold 60 W), or -1 if that never happens.
+ * The comparison is literal ("below threshold" breaks the condition), so NaN readings do
+ * not.  Integer result, independent of scheduling.  OPEN_E_INVALID for T < 0, L < 0,
+ * ld < L, n_window < 1 or a NaN threshold.
+ */
+open_status open_phase_detect(open_ctx *ctx, const float *power, int64_t T, int64_t L, int64_t ld, float threshold,
+                              int32_t n_window, int64_t *first_index);
+
+/*
  * Kernel variants and autotuning (the fold-in's batched solves, Section III-B.2, run one
  * kernel per size class of |O_i|; each class group has up to 4 compiled configurations:
  * lanes per system, waves per block, waves per SIMD).  The choice is per context and rank

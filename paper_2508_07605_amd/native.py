@@ -34,6 +34,7 @@ SIGNATURES = {
     "open_profile_read": (_I32, [_P, _P, _P, _P, _I32, _I32]),
     "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_foldin_graph": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
+    "open_phase_detect": (_I32, [_P, _P, _I64, _I64, _I64, _F32, _I32, _P]),
     "open_tune_info": (_I32, [_I32, _P, _P, _I32]),
     "open_tune_get": (_I32, [_P, _I32, _P, _I32]),
     "open_tune_set": (_I32, [_P, _I32, _P, _I32]),
@@ -185,6 +186,17 @@ def open_foldin_graph(ctx, F, row_ptr, col, val, lam, weighted=True, U_out=None,
                                       _dev(U_out, torch.float32, "U_out", m * k),
                                       _dev(row_status, torch.int32, "row_status", m)))
     return U_out
+
+
+def open_phase_detect(ctx, power, threshold=60.0, n_window=25, first_index=None):
+    """Algorithm 1 over the rows of a 2-D device tensor of power readings."""
+    T, L = power.shape
+    if first_index is None:
+        first_index = torch.empty(T, dtype=torch.int64, device=power.device)
+    ctx.check(lib().open_phase_detect(ctx.handle, _dev(power, torch.float32, "power", T * L), T, L,
+                                      power.stride(0) if T > 0 else L, float(threshold), int(n_window),
+                                      _dev(first_index, torch.int64, "first_index", T)))
+    return first_index
 
 
 def open_tune_info(k):

@@ -22,7 +22,7 @@ import numpy as np
 SEED_TAG = 20250811
 
 # independent random streams per configuration
-S_APPS, S_COUNTS, S_SETS, S_NOISE, S_INIT, S_MLP, S_REF, S_EVAL = range(8)
+S_APPS, S_COUNTS, S_SETS, S_NOISE, S_INIT, S_MLP, S_REF, S_EVAL, S_POWER = range(9)
 
 
 def rng(cfg_id: int, stream: int, seed: int = 0) -> np.random.Generator:
@@ -258,3 +258,23 @@ def latent_rows(cfg_id: int, grid: Grid, V: np.ndarray, m: int, seed: int = 0, n
     pick = r.integers(0, n_proto, size=m)
     U = proto[pick] + noise * r.standard_normal((m, V.shape[1]))
     return np.ascontiguousarray(U.astype(np.float32))
+
+
+# ----------------------------------------------------------------------------- power traces
+def power_traces(cfg_id: int, T: int, L: int, seed: int = 0, p_never: float = 0.1,
+                 p_dip: float = 0.01) -> np.ndarray:
+    """GPU power readings (W), T traces x L samples, float32: a CPU-side phase of random length
+    at 25-55 W, then a GPU phase at 120-280 W with rare dips to 20-59 W (data loading, sync);
+    a fraction p_never of the traces stays in the CPU phase.  Stand-in for the paper's power
+    patterns of applications with long CPU phases (Fig. 5)."""
+    r = rng(cfg_id, S_POWER, seed)
+    start = r.integers(0, L, size=T)
+    start[r.random(T) < p_never] = L
+    lo = r.uniform(25.0, 55.0, size=(T, 1))
+    hi = r.uniform(120.0, 280.0, size=(T, 1))
+    t = np.arange(L)[None, :]
+    gpu = t >= start[:, None]
+    p = np.where(gpu, hi, lo) + r.normal(0.0, 3.0, size=(T, L))
+    dip = gpu & (r.random((T, L)) < p_dip)
+    p = np.where(dip, r.uniform(20.0, 59.0, size=(T, L)), p)
+    return np.ascontiguousarray(p.astype(np.float32))
