@@ -233,6 +233,55 @@ def phase_leg(ctx, steps, warmup, log):
                          "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": byts}}
 
 
+def refit_leg(ctx, state, log):
+    """Warm-started refit: 50k new apps (4-24 observed each) arrive at the fitted 200k x 480
+    matrix; fold-in alone vs fold-in + 2 ALS sweeps on the union, timed, with the RMSE of both
+    against the noiseless truth on the new apps' unobserved settings."""
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    c, grid, rows, dU, dV = state
+    k, lam = c["k"], c["lam"]
+    new = synth.draw_rows(c["cfg_id"], grid, 50_000, ("uniform", 4, 24), seed=1)
+    rp = np.concatenate([rows.row_ptr, rows.row_ptr[-1] + new.row_ptr[1:]])
+    col = np.concatenate([rows.col, new.col])
+    val = np.concatenate([rows.val, new.val])
+    dev = dU.device
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    drp, dcol, dval = to(rp), to(col), to(val)
+    m_old, m = rows.m, rows.m + new.m
+    U_f = torch.cat([dU, torch.zeros((new.m, k), dtype=torch.float32, device=dev)])
+    V_f = dV.clone()
+    native.open_refit(ctx, m_old, drp, dcol, dval, U_f, V_f, lam, 0)  # fold-in only
+    U_r, V_r = U_f.clone(), dV.clone()
+    U_r[m_old:] = 0
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    native.open_refit(ctx, m_old, drp, dcol, dval, U_r, V_r, lam, 2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ev = np.sort(np.random.default_rng(5).choice(new.m, size=10_000, replace=False))
+    T = synth.truth_dense(new.apps.take(ev), grid)
+    obs = np.zeros_like(T, dtype=bool)
+    for j, i in enumerate(ev):
+        obs[j, new.col[new.row_ptr[i]:new.row_ptr[i + 1]]] = True
+    idx = torch.from_numpy(ev + m_old).to(dev)
+
+    def rmse(U, V):
+        P = (U[idx].double() @ V.double().T).cpu().numpy()
+        return float(np.sqrt(((P - T)[~obs] ** 2).mean()))
+
+    r_f, r_r = rmse(U_f, V_f), rmse(U_r, V_r)
+    log("refit: 2 sweeps on %d rows in %.2f ms; new-app RMSE fold-in %.5f, refit %.5f" % (m, ms, r_f, r_r))
+    return {"workload": "warm refit: %d offline + %d new apps x %d settings, rank %d, 2 sweeps" %
+                        (m_old, new.m, grid.n, k),
+            "ms": ms, "rmse_new_foldin": r_f, "rmse_new_refit": r_r, "drift": r_f - r_r}
+
+
 def fit_leg(args, ctx, log):
     """ALS-WR fit on 200k apps x 480 settings, truncated Zipf(1.2) observed counts on [3, 480]
     (12.7M observed entries), rank 32, weighted lambda 0.05: time per sweep (rows, then
@@ -278,7 +327,8 @@ def fit_leg(args, ctx, log):
     ccount = np.bincount(rows.col, minlength=grid.n)
     flops = float(row_flops(rows.counts(), k).sum() + row_flops(ccount, k).sum())
     tf = flops / (ms * 1e-3) / 1e12
-    return {"workload": "ALS-WR fit: %d apps x %d settings, Zipf(1.2) counts on [3, 480], %d nnz, rank %d, "
+    state = (c, grid, rows, dU, dV)
+    return state, {"workload": "ALS-WR fit: %d apps x %d settings, Zipf(1.2) counts on [3, 480], %d nnz, rank %d, "
                         "weighted lambda %g" % (rows.m, grid.n, rows.nnz, k, lam),
             "ms_per_sweep": ms, "setup_ms_per_call": setup_ms, "sweeps_timed": S, "objective_after": obj,
             "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -448,7 +498,9 @@ def main():
         log("phase detection %.3e traces/s, %.0f GB/s" % (out["phase_detect"]["traces_per_s"],
                                                            out["phase_detect"]["roofline"]["achieved"]))
     if not args.no_fit:
-        out["fit"] = fit_leg(args, ctx, log)
+        fit_state, out["fit"] = fit_leg(args, ctx, log)
+        out["refit"] = refit_leg(ctx, fit_state, log)
+        del fit_state
         log("fit %.3f ms/sweep, %.1f TFLOP/s" % (out["fit"]["ms_per_sweep"], out["fit"]["roofline"]["achieved"]))
     U_sur = None
     if not args.no_surrogate:

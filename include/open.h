@@ -146,6 +146,18 @@ open_status open_autotune(open_ctx *ctx, const float *F, int32_t n, int32_t k, i
                           int32_t *row_status, int32_t reps, double *ms_out);
 
 /*
+ * Warm-started refit (Section III-B.2: new applications expand the matrix, which is then
+ * completed): the CSR holds the m_old offline rows first, then the m_new new rows.  U
+ * (device, (m_old + m_new) x k) holds the fitted offline factors in its first m_old rows on
+ * entry; V (n x k) the fitted setting factors.  The new rows are folded in against V
+ * (open_foldin), then `sweeps` ALS-WR sweeps run on the union (open_fit, same conventions),
+ * updating U and V.  sweeps = 0 leaves the plain fold-in.
+ */
+open_status open_refit(open_ctx *ctx, int64_t m_old, int64_t m_new, int32_t n, int32_t k, const int64_t *row_ptr,
+                       const int32_t *col, const float *val, float lambda, int32_t weighted, int32_t sweeps, float *U,
+                       float *V, double *obj_hist);
+
+/*
  * Column view of a CSR matrix (m x n): col_ptr int64[n+1], row_idx int32[nnz] and
  * cval float32[nnz], entries ordered by column and, within a column, by row.  Exact
  * integer work (a stable counting sort).  All pointers are device pointers.

@@ -504,4 +504,20 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
   return st;
 }
 
+// Warm-started refit on the union of the offline rows and newly arrived rows: the new rows are
+// folded in against the current V, then `sweeps` ALS sweeps run on the union from there.
+open_status open_refit(open_ctx *ctx, int64_t m_old, int64_t m_new, int32_t n, int32_t k, const int64_t *row_ptr,
+                       const int32_t *col, const float *val, float lambda, int32_t weighted, int32_t sweeps, float *U,
+                       float *V, double *obj_hist) {
+  if (!ctx) return OPEN_E_INVALID;
+  if (m_old < 0 || m_new < 0 || m_old + m_new <= 0 || !U || !V || !row_ptr)
+    return fail(ctx, OPEN_E_INVALID, "bad shape or pointer");
+  open_status st;
+  if (m_new > 0 &&
+      (st = open_foldin(ctx, V, n, k, m_new, row_ptr + m_old, col, val, lambda, weighted, U + m_old * (int64_t)k,
+                        nullptr)))
+    return st;
+  return open_fit(ctx, m_old + m_new, n, k, row_ptr, col, val, lambda, weighted, sweeps, U, V, obj_hist);
+}
+
 }  // extern "C"

@@ -35,6 +35,7 @@ SIGNATURES = {
     "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_foldin_graph": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_phase_detect": (_I32, [_P, _P, _I64, _I64, _I64, _F32, _I32, _P]),
+    "open_refit": (_I32, [_P, _I64, _I64, _I32, _I32, _P, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
     "open_tune_info": (_I32, [_I32, _P, _P, _I32]),
     "open_tune_get": (_I32, [_P, _I32, _P, _I32]),
     "open_tune_set": (_I32, [_P, _I32, _P, _I32]),
@@ -253,6 +254,20 @@ def open_fit(ctx, row_ptr, col, val, U, V, lam, sweeps, weighted=True, want_obj=
                              int(bool(weighted)), int(sweeps), _dev(U, torch.float32, "U", m * k),
                              _dev(V, torch.float32, "V", n * k),
                              obj.ctypes.data_as(ctypes.c_void_p) if obj is not None else None))
+    return obj
+
+
+def open_refit(ctx, m_old, row_ptr, col, val, U, V, lam, sweeps, weighted=True, want_obj=False):
+    """Fold the rows after the first m_old into U against V, then `sweeps` ALS sweeps on all."""
+    import numpy as np
+    m, k = U.shape
+    n = V.shape[0]
+    obj = np.zeros(2 * max(sweeps, 0)) if want_obj else None
+    ctx.check(lib().open_refit(ctx.handle, int(m_old), m - int(m_old), n, k,
+                               _dev(row_ptr, torch.int64, "row_ptr", m + 1), _dev(col, torch.int32, "col"),
+                               _dev(val, torch.float32, "val"), float(lam), int(bool(weighted)), int(sweeps),
+                               _dev(U, torch.float32, "U", m * k), _dev(V, torch.float32, "V", n * k),
+                               obj.ctypes.data_as(ctypes.c_void_p) if obj is not None else None))
     return obj
 
 

@@ -136,3 +136,31 @@ def test_fit_graph_replay_matches_eager(ctx):
     Ue, Ve = dev(U0), dev(V0)
     native.open_fit(ctx, *args, Ue, Ve, c["lam"], 4, True, want_obj=True)
     assert torch.equal(Ug, Ue) and torch.equal(Vg, Ve)
+
+
+@pytest.mark.parametrize("sweeps", [0, 2])
+def test_refit_warm_start(ctx, sweeps):
+    # offline rows + newly arrived rows: fold-in of the new rows against V, then ALS sweeps on
+    # the union from the offline factors, against the oracle doing the same steps in FP64
+    c, grid, rows = fit_rows("fit", m=5_000, seed=13)
+    m_old = 4_000
+    U0, V0 = synth.init_factors(c["cfg_id"], rows.m, grid.n, c["k"], seed=13)
+    U, V = dev(U0), dev(V0)
+    obj = native.open_refit(ctx, m_old, dev(rows.row_ptr), dev(rows.col), dev(rows.val), U, V, c["lam"], sweeps,
+                            True, want_obj=sweeps > 0)
+    rp_new = rows.row_ptr[m_old:] - rows.row_ptr[m_old]
+    seg = slice(int(rows.row_ptr[m_old]), int(rows.row_ptr[-1]))
+    Unew, _ = oracle.ridge_rows(rp_new, rows.col[seg], rows.val[seg], V0, c["lam"], True)
+    Ui = np.concatenate([U0[:m_old].astype(np.float64), Unew])
+    if sweeps == 0:
+        Ur, Vr = Ui, V0.astype(np.float64)
+    else:
+        Ur, Vr, objr = oracle.fit(rows.row_ptr, rows.col, rows.val, Ui, V0, c["lam"], sweeps, True)
+    Ug, Vg = host(U).astype(np.float64), host(V).astype(np.float64)
+    pe = fro_rel(Ug @ Vg.T, Ur @ Vr.T)
+    print("refit sweeps=%d: UV^T %.3e" % (sweeps, pe))
+    assert pe <= 1e-4
+    if sweeps > 0:
+        assert np.abs(obj - objr).max() / objr.max() <= 1e-4
+    else:
+        assert np.array_equal(host(U)[:m_old], U0[:m_old])
