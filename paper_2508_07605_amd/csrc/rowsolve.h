@@ -89,7 +89,7 @@ __host__ __device__ constexpr int wave_lds_floats(int P, int D) {
   return (P < 4 ? 16 * tri_stride(D) : 0) + 2 * (64 / P) * (D + 1);
 }
 
-template <int P, int D, int K, bool DUAL, bool LDSF, bool PF>
+template <int P, int D, int K, bool DUAL, bool LDSF, bool PF, bool BLK>
 __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, const RowRef mine,
                                             const int32_t *__restrict__ idx, const float *__restrict__ val,
                                             float lambda, int weighted, float *__restrict__ X,
@@ -293,57 +293,128 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
 
   // ---- elimination with fused forward substitution
   int bad = 0;
-  sfor<0, D>([&](auto Pp) {
-    constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
-    const float d = grp_bcast<P, pp>(st[mp][pp]);
-    bad |= !(d > 0.f);
-    const float s = __builtin_amdgcn_rcpf(d);
-    const float ty = -s * grp_bcast<P, pp>(bm[mp]);  // -b[p] / d
-    if constexpr (P == 1) {
-      // the pivot column is the lane's own: update every later column
-      sfor<p + 1, D>([&](auto C) {
-        constexpr int c = decltype(C)::value;
-        const float lc = st[mp][c - mp] * (-s);  // -G[c][p] / d
-        bm[c] = __builtin_fmaf(st[mp][c - mp], ty, bm[c]);
-        sfor<c, D>([&](auto R) {
+  if constexpr (BLK) {
+    // Blocked by tile columns (four lanes per system).  The four pivots of tile column t update
+    // only that tile column (the panel); the trailing tiles then get the rank-4 update
+    //   G[4I+i][4J+j] -= sum_q Gp[4I+i][4t+q] Gp[4J+j][4t+q] / d_q   (I >= J > t)
+    // on MFMA, Gp being the panel column at its pivot.  The instruction needs row i of a
+    // panel tile in lane i; four MFMAs against unit vectors transpose a tile in the quad.
+    static_assert(P == 4 && DUAL, "the blocked elimination works on the four-lane dual layout");
+    sfor<0, N>([&](auto Tt) {
+      constexpr int t = decltype(Tt)::value;
+      float sv[4], tyv[4];  // 1 / d_q and -b_q / d_q of the tile's pivots
+      sfor<0, 4>([&](auto PPp) {
+        constexpr int pp = decltype(PPp)::value, p = 4 * t + pp;
+        const float d = quad_bcast_c<pp>(st[t][pp]);
+        bad |= !(d > 0.f);
+        const float sp = __builtin_amdgcn_rcpf(d);
+        const float ty = -sp * quad_bcast_c<pp>(bm[t]);
+        sv[pp] = sp;
+        tyv[pp] = ty;
+        float g[D];
+        sfor<p + 1, D>([&](auto R) {
           constexpr int r = decltype(R)::value;
-          st[c][r - c] = __builtin_fmaf(st[mp][r - mp], lc, st[c][r - c]);
+          g[r] = quad_bcast_c<pp>(st[t][r - 4 * t]);
         });
-      });
-    } else {
-      // column p below the pivot, broadcast from its owner lane: g[r] = G[r][p]
-      float g[D];
-      sfor<p + 1, D>([&](auto R) {
-        constexpr int r = decltype(R)::value;
-        g[r] = grp_bcast<P, pp>(st[mp][r - P * mp]);
-      });
-      // owned columns c = P m + pi: multiplier -G[c][p] / d and rhs, no-ops for c <= p
-      float lc[M];
-      sfor<mp, M>([&](auto Mm) {
-        constexpr int m = decltype(Mm)::value;
-        float cand[P];
-        sfor<0, P>([&](auto k) {
-          constexpr int c = P * m + decltype(k)::value;
+        float cand[4];
+        sfor<0, 4>([&](auto k) {
+          constexpr int c = 4 * t + decltype(k)::value;
           if constexpr (c > p)
             cand[k] = g[c];
           else
             cand[k] = 0.f;
         });
-        const float go = pick<P>(cand, pi);
-        lc[m] = go * (-s);
-        bm[m] = __builtin_fmaf(go, ty, bm[m]);
+        const float go = pick<4>(cand, pi);
+        bm[t] = __builtin_fmaf(go, ty, bm[t]);
+        if constexpr (pp < 3) {
+          const float lc = go * (-sp);
+          sfor<p + 1, D>([&](auto R) {
+            constexpr int r = decltype(R)::value;
+            st[t][r - 4 * t] = __builtin_fmaf(g[r], lc, st[t][r - 4 * t]);
+          });
+        }
       });
-      // the pivot's own tile column is finished when p is its last column (lc = 0 there)
-      constexpr int m0 = pp == P - 1 ? mp + 1 : mp;
-      sfor<p + 1, D>([&](auto R) {
-        constexpr int r = decltype(R)::value;
-        sfor<m0, (r / P + 1 < M ? r / P + 1 : M)>([&](auto Mm) {
-          constexpr int m = decltype(Mm)::value;
-          st[m][r - P * m] = __builtin_fmaf(g[r], lc[m], st[m][r - P * m]);
+      if constexpr (t + 1 < N) {
+        f4 tt[N], ts[N];  // transposed panel tiles (lane = row, register = panel column), scaled copy
+        sfor<t + 1, N>([&](auto Ii) {
+          constexpr int I = decltype(Ii)::value;
+          f4 x = f4{0.f, 0.f, 0.f, 0.f};
+          sfor<0, 4>([&](auto S) {
+            constexpr int s_ = decltype(S)::value;
+            x = mfma4x4(st[t][4 * (I - t) + s_], qi == s_ ? 1.f : 0.f, x);
+          });
+          tt[I] = x;
+          f4 y;
+          sfor<0, 4>([&](auto q) {
+            y[(int)q] = x[(int)q] * (-sv[q]);
+            bm[I] = __builtin_fmaf(x[(int)q], tyv[q], bm[I]);  // trailing right-hand side
+          });
+          ts[I] = y;
         });
-      });
-    }
-  });
+        sfor<t + 1, N>([&](auto Ii) {
+          constexpr int I = decltype(Ii)::value;
+          sfor<t + 1, I + 1>([&](auto Jj) {
+            constexpr int J = decltype(Jj)::value, o = 4 * (I - J);
+            f4 a = f4{st[J][o], st[J][o + 1], st[J][o + 2], st[J][o + 3]};
+            sfor<0, 4>([&](auto q) { a = mfma4x4(tt[I][(int)q], ts[J][(int)q], a); });
+            sfor<0, 4>([&](auto v) { st[J][o + v] = a[(int)v]; });
+          });
+        });
+      }
+    });
+  } else {
+    sfor<0, D>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
+      const float d = grp_bcast<P, pp>(st[mp][pp]);
+      bad |= !(d > 0.f);
+      const float s = __builtin_amdgcn_rcpf(d);
+      const float ty = -s * grp_bcast<P, pp>(bm[mp]);  // -b[p] / d
+      if constexpr (P == 1) {
+        // the pivot column is the lane's own: update every later column
+        sfor<p + 1, D>([&](auto C) {
+          constexpr int c = decltype(C)::value;
+          const float lc = st[mp][c - mp] * (-s);  // -G[c][p] / d
+          bm[c] = __builtin_fmaf(st[mp][c - mp], ty, bm[c]);
+          sfor<c, D>([&](auto R) {
+            constexpr int r = decltype(R)::value;
+            st[c][r - c] = __builtin_fmaf(st[mp][r - mp], lc, st[c][r - c]);
+          });
+        });
+      } else {
+        // column p below the pivot, broadcast from its owner lane: g[r] = G[r][p]
+        float g[D];
+        sfor<p + 1, D>([&](auto R) {
+          constexpr int r = decltype(R)::value;
+          g[r] = grp_bcast<P, pp>(st[mp][r - P * mp]);
+        });
+        // owned columns c = P m + pi: multiplier -G[c][p] / d and rhs, no-ops for c <= p
+        float lc[M];
+        sfor<mp, M>([&](auto Mm) {
+          constexpr int m = decltype(Mm)::value;
+          float cand[P];
+          sfor<0, P>([&](auto k) {
+            constexpr int c = P * m + decltype(k)::value;
+            if constexpr (c > p)
+              cand[k] = g[c];
+            else
+              cand[k] = 0.f;
+          });
+          const float go = pick<P>(cand, pi);
+          lc[m] = go * (-s);
+          bm[m] = __builtin_fmaf(go, ty, bm[m]);
+        });
+        // the pivot's own tile column is finished when p is its last column (lc = 0 there)
+        constexpr int m0 = pp == P - 1 ? mp + 1 : mp;
+        sfor<p + 1, D>([&](auto R) {
+          constexpr int r = decltype(R)::value;
+          sfor<m0, (r / P + 1 < M ? r / P + 1 : M)>([&](auto Mm) {
+            constexpr int m = decltype(Mm)::value;
+            st[m][r - P * m] = __builtin_fmaf(g[r], lc[m], st[m][r - P * m]);
+          });
+        });
+      }
+    });
+  }
 
   // ---- back substitution; dot[m] accumulates sum_{r > c} G[r][c] x_r for owned column c.
   // Dual systems fold each x_p into u = F_O^T x as soon as it is known: lane pi forms the
@@ -411,7 +482,7 @@ __host__ __device__ constexpr int wave_bytes() { return wave_lds_floats(P, D) * 
 
 // Persistent kernel over the rows of classes c_lo..c_hi (contiguous in the bucketed list),
 // all solved at padded dimension D (dual) or k (primal).
-template <int K, int P, int D, bool DUAL, bool LDSF, int W, int OCC>
+template <int K, int P, int D, bool DUAL, bool LDSF, int W, int OCC, bool BLK>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_waves_per_eu(OCC))) void k_solve_class(const float *__restrict__ F, int n,
                                                      const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                      const float *__restrict__ val, const RowRef *__restrict__ list,
@@ -460,7 +531,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_wa
   for (int64_t g = g0; g * SYS < count; g += nw) {
     const RowRef nxt = fetch(g + nw);  // next group's records load while this group computes
     // operand prefetch in the Gram loop when a single wave per SIMD has to hide the latency
-    solve_group<P, D, K, DUAL, LDSF, (OCC == 1 || D <= 12)>(Fr, n, cur, idx, val, lambda, weighted, X, status, wl);
+    solve_group<P, D, K, DUAL, LDSF, (OCC == 1 || D <= 12), BLK>(Fr, n, cur, idx, val, lambda, weighted, X, status,
+                                                                 wl);
     cur = nxt;
   }
 }
@@ -468,7 +540,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_wa
 // Launch the kernel of one size class with a persistent grid sized for m rows: blocks of W
 // waves (sharing one LDS copy of the factors), as many per CU as LDS and the register
 // budget of OCC waves per SIMD allow.
-template <int K, int P, int D, bool DUAL, int W = 4, int OCC = 1>
+template <int K, int P, int D, bool DUAL, int W = 4, int OCC = 1, bool BLK = false>
 open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n, const int64_t *ptr,
                          const int32_t *idx, const float *val, float lambda, int weighted, const RowRef *list,
                          const int64_t *cls, int c_lo, int c_hi, float *X, int32_t *status, int64_t m) {
@@ -489,12 +561,12 @@ open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n,
   if (blocks < 1) blocks = 1;
   if constexpr (fl_fits) {
     if (fl) {
-      OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, true, W, OCC>), dim3((unsigned)blocks), dim3(64 * W), 0,
+      OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, true, W, OCC, BLK>), dim3((unsigned)blocks), dim3(64 * W), 0,
                   F, n, ptr, idx, val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
       return OPEN_OK;
     }
   }
-  OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, false, W, OCC>), dim3((unsigned)blocks), dim3(64 * W), 0, F,
+  OPEN_LAUNCH(ctx, name, (k_solve_class<K, P, D, DUAL, false, W, OCC, BLK>), dim3((unsigned)blocks), dim3(64 * W), 0, F,
               n, ptr, idx, val, list, cls, c_lo, c_hi, lambda, weighted, X, status);
   return OPEN_OK;
 }
@@ -505,9 +577,10 @@ open_status launch_class(const char *name, open_ctx *ctx, const float *F, int n,
 #define OPEN_TIER_PASS ctx, F, n, ptr, idx, val, lambda, weighted, list, cls
 
 // ---------------------------------------------------------------- kernel variants
-// A kernel configuration in one integer: P lanes per system, W waves per block, and OCC
-// waves per SIMD that the register allocation must allow.
-constexpr int cfg(int P, int W, int OCC) { return P * 10000 + W * 100 + OCC; }
+// A kernel configuration in one integer: P lanes per system, W waves per block, OCC waves per
+// SIMD that the register allocation must allow, and BLK for the blocked (MFMA trailing
+// update) elimination.
+constexpr int cfg(int P, int W, int OCC, int BLK = 0) { return BLK * 1000000 + P * 10000 + W * 100 + OCC; }
 
 // Launch configuration number `choice` of C... for one class group.
 template <int K, int D, bool DUAL, int... C>
@@ -515,7 +588,7 @@ open_status launch_variant(int choice, const char *name, int c_lo, int c_hi, OPE
   open_status st = OPEN_OK;
   int i = 0;
   bool done = false;
-  ((i++ == choice ? (void)(done = true, st = launch_class<K, C / 10000, D, DUAL, (C / 100) % 100, C % 100>(
+  ((i++ == choice ? (void)(done = true, st = launch_class<K, (C / 10000) % 100, D, DUAL, (C / 100) % 100, C % 100, (C / 1000000) != 0>(
                                             name, OPEN_TIER_PASS, c_lo, c_hi, X, status, m))
                   : (void)0),
    ...);

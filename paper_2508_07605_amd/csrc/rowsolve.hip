@@ -25,9 +25,9 @@ const ClassGroup *class_groups(int k, int *count) {
       {"ridge_k32_d4", 0, 1, 2, g_k32_d4},
       {"ridge_k32_d8", 2, 2, 2, g_k32_d8},
       {"ridge_k32_d12", 3, 3, 2, g_k32_d12},
-      {"ridge_k32_d16", 4, 4, 3, g_k32_d16},
-      {"ridge_k32_d20", 5, 5, 3, g_k32_d20},
-      {"ridge_k32_d24", 6, 6, 3, g_k32_d24},
+      {"ridge_k32_d16", 4, 4, 4, g_k32_d16},
+      {"ridge_k32_d20", 5, 5, 4, g_k32_d20},
+      {"ridge_k32_d24", 6, 6, 4, g_k32_d24},
       {"ridge_k32_d28", 7, 7, 2, g_k32_d28},
       {"ridge_k32_d32", 8, 8, 2, g_k32_d32},
       {"ridge_k32_primal", 9, 15, 2, g_k32_primal},

@@ -5,7 +5,7 @@
 namespace openk {
 
 OPEN_GROUP(g_k32_d16) {
-  return launch_variant<32, 16, true, cfg(4, 16, 4), cfg(4, 8, 2), cfg(1, 4, 1)>(choice, "ridge_k32_d16", 4, 4, OPEN_TIER_PASS, X,
+  return launch_variant<32, 16, true, cfg(4, 16, 4), cfg(4, 8, 2), cfg(1, 4, 1), cfg(4, 16, 4, 1)>(choice, "ridge_k32_d16", 4, 4, OPEN_TIER_PASS, X,
                        status, m);
 }
 

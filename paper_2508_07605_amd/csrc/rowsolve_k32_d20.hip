@@ -5,7 +5,7 @@
 namespace openk {
 
 OPEN_GROUP(g_k32_d20) {
-  return launch_variant<32, 20, true, cfg(4, 12, 3), cfg(4, 8, 2), cfg(2, 4, 1)>(choice, "ridge_k32_d20", 5, 5, OPEN_TIER_PASS, X,
+  return launch_variant<32, 20, true, cfg(4, 12, 3), cfg(4, 8, 2), cfg(2, 4, 1), cfg(4, 8, 2, 1)>(choice, "ridge_k32_d20", 5, 5, OPEN_TIER_PASS, X,
                        status, m);
 }
 
