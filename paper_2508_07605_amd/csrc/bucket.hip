@@ -15,8 +15,12 @@ __global__ void k_fill_i32(int *p, int64_t n, int v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-constexpr int kRowsPerBlock = 2048;
-constexpr int kBucketThreads = 256;
+constexpr int kRowsPerBlock = 4096;
+constexpr int kBucketThreads = 512;
+constexpr int kRowsPerWave = kRowsPerBlock / (kBucketThreads / kWave);  // contiguous rows of one wave
+// Up to this many blocks the place kernel derives its own offsets from the raw histogram
+// (each block reads kNumClasses * nblk counts from L2), so no scan launch is needed.
+constexpr int kSelfScanMaxBlocks = 256;
 
 __device__ __forceinline__ int row_class(int64_t cnt, int k, int64_t split_min) {
   if (cnt <= 0) return 0;
@@ -29,27 +33,61 @@ __device__ __forceinline__ int row_class(int64_t cnt, int k, int64_t split_min) 
   return 9 + p;
 }
 
-// mask (nullable): rows with mask[i] == 0 are left out of every class
-__device__ __forceinline__ int row_class_m(const int64_t *__restrict__ ptr, const uint8_t *__restrict__ mask, int64_t i,
-                                           int k, int64_t split_min) {
-  if (mask && !mask[i]) return -1;
-  return row_class(ptr[i + 1] - ptr[i], k, split_min);
+// mask (nullable): rows with mask[i] == 0 are left out of every class (class -1)
+constexpr int kPasses = kRowsPerWave / kWave;
+
+// The rows of one wave (kPasses rows per lane, rows wbase + 64 p + lane): all row-pointer
+// loads are issued before any is used, so the latency is paid once rather than per pass.
+struct WaveRows {
+  int c[kPasses];
+  int64_t beg[kPasses];
+  int cnt[kPasses];
+};
+__device__ __forceinline__ void load_wave_rows(WaveRows &r, int64_t m, const int64_t *__restrict__ ptr,
+                                               const uint8_t *__restrict__ mask, int k, int64_t split_min,
+                                               int64_t wbase, int lane) {
+  int64_t hi[kPasses];
+  uint8_t keep[kPasses];
+#pragma unroll
+  for (int p = 0; p < kPasses; ++p) {
+    const int64_t i = wbase + p * kWave + lane;
+    const bool in = i < m;
+    r.beg[p] = in ? ptr[i] : 0;
+    hi[p] = in ? ptr[i + 1] : 0;
+    keep[p] = in ? (mask ? mask[i] : (uint8_t)1) : (uint8_t)0;
+  }
+#pragma unroll
+  for (int p = 0; p < kPasses; ++p) {
+    const int64_t n = hi[p] - r.beg[p];
+    r.cnt[p] = (int)n;
+    r.c[p] = keep[p] ? row_class(n, k, split_min) : -1;
+  }
+}
+
+// per-class count of the wave's rows, class cc held by lane cc
+__device__ __forceinline__ int wave_class_counts(const WaveRows &r, int lane) {
+  int mine = 0;
+#pragma unroll
+  for (int p = 0; p < kPasses; ++p)
+    for (int cc = 0; cc < kNumClasses; ++cc) {
+      const int n = __popcll(__ballot(r.c[p] == cc));
+      mine += lane == cc ? n : 0;
+    }
+  return mine;
 }
 
 __global__ __launch_bounds__(kBucketThreads) void k_class_count(int64_t m, const int64_t *__restrict__ ptr,
                                                                 const uint8_t *__restrict__ mask, int k,
                                                                 int64_t split_min, int32_t *__restrict__ hist) {
   __shared__ int h[kNumClasses];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x < kNumClasses) h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock;
-  for (int r = threadIdx.x; r < kRowsPerBlock; r += kBucketThreads) {
-    const int64_t i = base + r;
-    if (i < m) {
-      const int c = row_class_m(ptr, mask, i, k, split_min);
-      if (c >= 0) atomicAdd(&h[c], 1);
-    }
-  }
+  WaveRows r;
+  load_wave_rows(r, m, ptr, mask, k, split_min, (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)w * kRowsPerWave,
+                 lane);
+  const int mine = wave_class_counts(r, lane);
+  if (lane < kNumClasses) atomicAdd(&h[lane], mine);
   __syncthreads();
   if (threadIdx.x < kNumClasses) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
@@ -107,41 +145,81 @@ __global__ __launch_bounds__(1024) void k_class_scan(int32_t *__restrict__ hist,
   }
 }
 
+__device__ __forceinline__ int wave_sum_i(int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+// SELF_SCAN: `offs` holds the raw class-major counts; every block sums the counts of all
+// blocks (class totals) and of the blocks before it, and block 0 writes cls.  Otherwise
+// `offs` is the scanned histogram and cls was written by the scan.
+template <bool SELF_SCAN>
 __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const int64_t *__restrict__ ptr,
                                                                 const uint8_t *__restrict__ mask, int k,
                                                                 int64_t split_min, const int32_t *__restrict__ offs,
-                                                                RowRef *__restrict__ list) {
+                                                                RowRef *__restrict__ list, int64_t *__restrict__ cls) {
   __shared__ int wcnt[kBucketThreads / kWave][kNumClasses];
   __shared__ int run[kNumClasses];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid < kNumClasses) run[tid] = offs[(int64_t)tid * gridDim.x + blockIdx.x];
-  __syncthreads();
-  for (int pass = 0; pass < kRowsPerBlock / kBucketThreads; ++pass) {
-    const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + pass * kBucketThreads + tid;
-    const int c = i < m ? row_class_m(ptr, mask, i, k, split_min) : -1;
-    int rank = 0;
-    for (int cc = 0; cc < kNumClasses; ++cc) {
-      const unsigned long long mask = __ballot(c == cc);
-      if (c == cc) rank = __popcll(mask & ((1ull << lane) - 1ull));
-      if (lane == 0) wcnt[w][cc] = __popcll(mask);
-    }
-    __syncthreads();
-    if (c >= 0) {
-      int pos = run[c];
-      for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][c];
-      const int64_t beg = ptr[i];
-      list[pos + rank] = RowRef{(int32_t)i, (int32_t)(ptr[i + 1] - beg), beg};
+  if constexpr (SELF_SCAN) {
+    __shared__ int tot[kNumClasses], pre[kNumClasses];
+    const int nblk = (int)gridDim.x, me = (int)blockIdx.x;
+    for (int c = w; c < kNumClasses; c += kBucketThreads / kWave) {
+      int t = 0, p = 0;
+      for (int b = lane; b < nblk; b += kWave) {
+        const int h = offs[(int64_t)c * nblk + b];
+        t += h;
+        p += b < me ? h : 0;
+      }
+      t = wave_sum_i(t);
+      p = wave_sum_i(p);
+      if (lane == 0) {
+        tot[c] = t;
+        pre[c] = p;
+      }
     }
     __syncthreads();
     if (tid < kNumClasses) {
-      int add = 0;
-      for (int ww = 0; ww < kBucketThreads / kWave; ++ww) add += wcnt[ww][tid];
-      run[tid] += add;
+      int start = 0;
+      for (int c = 0; c < tid; ++c) start += tot[c];
+      run[tid] = start + pre[tid];
+      if (me == 0) {
+        cls[2 * tid] = start;
+        cls[2 * tid + 1] = tot[tid];
+      }
     }
-    __syncthreads();
+  } else {
+    if (tid < kNumClasses) run[tid] = offs[(int64_t)tid * gridDim.x + blockIdx.x];
+  }
+  // Each wave places its own contiguous rows: first its per-class counts (lane cc holds class
+  // cc), then, from its start within the block's run, the rows in order with ballot ranks.
+  const int64_t wbase = (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)w * kRowsPerWave;
+  WaveRows r;
+  load_wave_rows(r, m, ptr, mask, k, split_min, wbase, lane);
+  const int mine = wave_class_counts(r, lane);
+  if (lane < kNumClasses) wcnt[w][lane] = mine;
+  __syncthreads();
+  int pos = 0;
+  if (lane < kNumClasses) {
+    pos = run[lane];
+    for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][lane];
+  }
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int p = 0; p < kPasses; ++p) {
+    const int c = r.c[p];
+    int rank = 0, add = 0;
+    for (int cc = 0; cc < kNumClasses; ++cc) {
+      const unsigned long long bm = __ballot(c == cc);
+      if (c == cc) rank = __popcll(bm & below);
+      if (lane == cc) add = __popcll(bm);
+    }
+    const int base = __shfl(pos, c < 0 ? 0 : c, kWave);
+    if (c >= 0) list[base + rank] = RowRef{(int32_t)(wbase + p * kWave + lane), r.cnt[p], r.beg[p]};
+    pos += add;
   }
 }
-
 open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, RowRef **list, int64_t **cls,
                         int64_t split_min, const uint8_t *mask) {
   const int nblk = (int)((m + kRowsPerBlock - 1) / kRowsPerBlock);
@@ -155,10 +233,15 @@ open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k,
     OPEN_LAUNCH(ctx, "bucket_count", k_class_count, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask, k,
                 split_min, (int32_t *)hist);
   }
-  OPEN_LAUNCH(ctx, "bucket_scan", k_class_scan, dim3(1), dim3(1024), 0, (int32_t *)hist, nblk, (int64_t *)c);
-  if (m > 0) {
-    OPEN_LAUNCH(ctx, "bucket_place", k_class_place, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask, k,
-                split_min, (const int32_t *)hist, (RowRef *)lst);
+  if (m > 0 && nblk <= kSelfScanMaxBlocks) {
+    OPEN_LAUNCH(ctx, "bucket_place", k_class_place<true>, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask,
+                k, split_min, (const int32_t *)hist, (RowRef *)lst, (int64_t *)c);
+  } else {
+    OPEN_LAUNCH(ctx, "bucket_scan", k_class_scan, dim3(1), dim3(1024), 0, (int32_t *)hist, nblk, (int64_t *)c);
+    if (m > 0) {
+      OPEN_LAUNCH(ctx, "bucket_place", k_class_place<false>, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask,
+                  k, split_min, (const int32_t *)hist, (RowRef *)lst, (int64_t *)c);
+    }
   }
   *list = (RowRef *)lst;
   *cls = (int64_t *)c;

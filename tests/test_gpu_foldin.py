@@ -125,6 +125,36 @@ def test_full_size_sampled(ctx):
     assert np.isfinite(U).all()
 
 
+def test_many_rows_bucketing_paths(ctx):
+    # the row bucketing takes two routes: up to 256 blocks of 4096 rows the placement derives
+    # its offsets from the raw per-block counts, above that a separate scan runs first; both
+    # must give the same rows (a row's result does not depend on the batch it sits in)
+    r = np.random.default_rng(21)
+    n, k, m = 480, 32, 2_300_007
+    counts = np.where(r.random(m) < 0.6, 0, r.integers(1, 41, size=m)).astype(np.int64)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(counts)
+    nnz = int(rp[-1])
+    row_of = np.repeat(np.arange(m), counts)
+    j = np.arange(nnz) - rp[row_of]
+    col = ((r.integers(0, n, size=m)[row_of] + 11 * j) % n).astype(np.int32)  # distinct within a row
+    val = r.uniform(0.4, 1.0, size=nnz).astype(np.float32)
+    V = (r.normal(size=(n, k)) * 0.3).astype(np.float32)
+    U, st = run_gpu(ctx, V, rp, col, val, 0.05)
+    assert np.array_equal(st, np.where(counts == 0, 1, 0))
+    assert (U[counts == 0] == 0).all()
+    sample = np.sort(r.choice(np.flatnonzero(counts), size=4000, replace=False))
+    ref, _ = oracle.ridge_subset(sample, rp, col, val, V, 0.05, True)
+    e = rel_err(U[sample], ref)
+    report("2.3M rows (scan route)", e)
+    assert e.max() <= TOL
+    # the first 1M rows as a batch of their own (self-scan route) give the same rows bitwise
+    m1 = 1_000_003
+    U1, st1 = run_gpu(ctx, V, rp[:m1 + 1], col[:rp[m1]], val[:rp[m1]], 0.05)
+    assert np.array_equal(st1, st[:m1])
+    assert np.array_equal(U1, U[:m1])
+
+
 @pytest.mark.parametrize("k,n,maxc", [(8, 120, 120), (16, 120, 120), (32, 480, 480), (32, 600, 600),
                                       (64, 480, 32)])
 def test_every_kernel_variant(ctx, k, n, maxc):
