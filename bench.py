@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 HERE = os.path.dirname(os.path.abspath(__file__))
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 
 
 def dual_flops(n, k):
@@ -233,6 +234,42 @@ def phase_leg(ctx, steps, warmup, log):
                          "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": byts}}
 
 
+def predictor_leg(ctx, rows, grid, steps, warmup, log):
+    """Offline performance predictor (7 -> 64 -> 64 -> 1) over every profiled run of the fold-in
+    workload (one feature vector per observed entry): runs per second.  Algorithmic work per
+    run: 2 (7*64 + 64*64 + 64) = 9216 flop and 32 B of HBM (28 B of features, 4 B out); the
+    kernel issues twice the layer products on BF16 MFMA (two-part activations)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    t0 = time.time()
+    X = torch.from_numpy(synth.run_features(3, grid, rows.col)).cuda()
+    p = {k: torch.from_numpy(v).cuda() for k, v in synth.predictor_params(3, grid).items()}
+    n = X.shape[0]
+    log("predictor: %d runs in %.1f s" % (n, time.time() - t0))
+    y = torch.empty(n, dtype=torch.float32, device=X.device)
+    for _ in range(warmup):
+        native.open_perf_predict(ctx, X, p, y=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        native.open_perf_predict(ctx, X, p, y=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flops, byts = 9216.0 * n, 32.0 * n
+    tf = flops / (ms * 1e-3) / 1e12
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": "offline predictor 7-64-64-1 (ReLU) over the %d profiled runs of the fold-in workload" % n,
+            "runs_per_s": n / (ms * 1e-3), "ms_per_step": ms,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": byts,
+                         "bf16_mfma_tflops": round(tf, 2), "bf16_mfma_frac": round(tf / PEAK_BF16_TFLOPS, 4)}}
+
+
 def refit_leg(ctx, state, log):
     """Warm-started refit: 50k new apps (4-24 observed each) arrive at the fitted 200k x 480
     matrix; fold-in alone vs fold-in + 2 ALS sweeps on the union, timed, with the RMSE of both
@@ -353,6 +390,7 @@ def main():
     ap.add_argument("--no-predict", action="store_true", help="skip the predict + selection leg")
     ap.add_argument("--no-fit", action="store_true", help="skip the ALS fit leg")
     ap.add_argument("--no-phase", action="store_true", help="skip the Alg. 1 phase-detection leg")
+    ap.add_argument("--no-predictor", action="store_true", help="skip the offline performance predictor leg")
     ap.add_argument("--fit-sweeps", type=int, default=3, help="timed ALS sweeps in the fit leg")
     ap.add_argument("--surrogate-epochs", type=float, default=2.0,
                     help="training epochs over the 2M ALS fold-in targets (batch 4096, Adam 1e-3)")
@@ -497,6 +535,11 @@ def main():
         out["phase_detect"] = phase_leg(ctx, args.steps, args.warmup, log)
         log("phase detection %.3e traces/s, %.0f GB/s" % (out["phase_detect"]["traces_per_s"],
                                                            out["phase_detect"]["roofline"]["achieved"]))
+    if not args.no_predictor:
+        out["perf_predictor"] = predictor_leg(ctx, rows, grid, args.steps, args.warmup, log)
+        log("offline predictor %.3e runs/s, %.0f GB/s, %.1f TFLOP/s" % (
+            out["perf_predictor"]["runs_per_s"], out["perf_predictor"]["roofline"]["achieved"],
+            out["perf_predictor"]["roofline"]["bf16_mfma_tflops"]))
     if not args.no_fit:
         fit_state, out["fit"] = fit_leg(args, ctx, log)
         out["refit"] = refit_leg(ctx, fit_state, log)

@@ -260,6 +260,24 @@ open_status open_mlp_foldin(open_mlp *mlp, const float *F, int64_t m, const int6
                             const float *val, float tau, float lambda, int32_t weighted, float *U_out,
                             uint8_t *used_fallback, float *rho, int64_t *n_fallback);
 
+/*
+ * Offline performance predictor (Section III-A.2, "Performance Prediction Model"), batched
+ * over n_runs profiled runs.  Run r's seven features X[r*7 .. r*7+7) (device float32, in the
+ * order CPU power cap, GPU power cap, memory throughput, IPS, SM clock, DRAM active rate,
+ * FP active rate) give its predicted normalized performance y[r] (device float32[n_runs]):
+ *   z = (x - mu) * rs,  h1 = ReLU(W1 z + b1),  h2 = ReLU(W2 h1 + b2),  y = w3 . h2 + b3,
+ * mu, rs: device float32[7] (feature centring and inverse scale); W1 float32[64*7] and
+ * W2 float32[64*64] row-major (output unit major), used rounded to bfloat16 (nearest even);
+ * b1, b2, w3 float32[64]; b3 float32[1]; all on the device and owned by the caller.  The
+ * activations keep float32 precision (products of the bfloat16 weights with two-part
+ * activations, float32 accumulation).  A run with a non-finite feature gets y = NaN.
+ * Asynchronous on the context's stream.  OPEN_E_INVALID
+ * for n_runs < 0 or a null pointer (n_runs = 0 does nothing).
+ */
+open_status open_perf_predict(open_ctx *ctx, const float *X, int64_t n_runs, const float *mu, const float *rs,
+                              const float *W1, const float *b1, const float *W2, const float *b2, const float *w3,
+                              const float *b3, float *y);
+
 #ifdef __cplusplus
 }
 #endif

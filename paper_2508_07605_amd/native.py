@@ -35,6 +35,7 @@ SIGNATURES = {
     "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_foldin_graph": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_phase_detect": (_I32, [_P, _P, _I64, _I64, _I64, _F32, _I32, _P]),
+    "open_perf_predict": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "open_refit": (_I32, [_P, _I64, _I64, _I32, _I32, _P, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
     "open_tune_info": (_I32, [_I32, _P, _P, _I32]),
     "open_tune_get": (_I32, [_P, _I32, _P, _I32]),
@@ -198,6 +199,21 @@ def open_phase_detect(ctx, power, threshold=60.0, n_window=25, first_index=None)
                                       power.stride(0) if T > 0 else L, float(threshold), int(n_window),
                                       _dev(first_index, torch.int64, "first_index", T)))
     return first_index
+
+
+def open_perf_predict(ctx, X, params, y=None):
+    """Offline predictor over the rows of X (device float32 [runs, 7]); params holds device
+    float32 tensors mu[7], rs[7], W1[64, 7], b1[64], W2[64, 64], b2[64], w3[64], b3[1]."""
+    n = X.shape[0]
+    if X.dim() != 2 or X.shape[1] != 7:
+        raise ValueError("X must be [runs, 7]")
+    if y is None:
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+    sizes = {"mu": 7, "rs": 7, "W1": 448, "b1": 64, "W2": 4096, "b2": 64, "w3": 64, "b3": 1}
+    ptrs = [_dev(params[name], torch.float32, name, cnt) for name, cnt in sizes.items()]
+    ctx.check(lib().open_perf_predict(ctx.handle, _dev(X, torch.float32, "X", n * 7), n, *ptrs,
+                                      _dev(y, torch.float32, "y", n)))
+    return y
 
 
 def open_tune_info(k):

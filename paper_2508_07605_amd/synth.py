@@ -22,7 +22,7 @@ import numpy as np
 SEED_TAG = 20250811
 
 # independent random streams per configuration
-S_APPS, S_COUNTS, S_SETS, S_NOISE, S_INIT, S_MLP, S_REF, S_EVAL, S_POWER = range(9)
+S_APPS, S_COUNTS, S_SETS, S_NOISE, S_INIT, S_MLP, S_REF, S_EVAL, S_POWER, S_COUNTERS, S_PRED = range(11)
 
 
 def rng(cfg_id: int, stream: int, seed: int = 0) -> np.random.Generator:
@@ -278,3 +278,39 @@ def power_traces(cfg_id: int, T: int, L: int, seed: int = 0, p_never: float = 0.
     dip = gpu & (r.random((T, L)) < p_dip)
     p = np.where(dip, r.uniform(20.0, 59.0, size=(T, L)), p)
     return np.ascontiguousarray(p.astype(np.float32))
+
+
+# ----------------------------------------------------------------------------- offline predictor
+# Feature ranges of a profiled run besides the two caps (uniform draws): memory throughput
+# (GB/s), instructions per second, SM clock (MHz), DRAM active rate, FP active rate.
+COUNTER_RANGES = ((50.0, 1500.0), (1.0e9, 5.0e10), (800.0, 1410.0), (0.0, 1.0), (0.0, 1.0))
+
+
+def run_features(cfg_id: int, grid: Grid, setting: np.ndarray, seed: int = 0) -> np.ndarray:
+    """Seven features per profiled run (float32 [runs, 7]): the CPU and GPU caps of the run's
+    setting, then synthetic counter readings (COUNTER_RANGES).  Stand-in for the counters the
+    paper collects online (Table I); no real counter data is available."""
+    r = rng(cfg_id, S_COUNTERS, seed)
+    setting = np.asarray(setting, dtype=np.int64)
+    X = np.empty((len(setting), 7), dtype=np.float32)
+    X[:, 0] = grid.cpu_w[setting]
+    X[:, 1] = grid.gpu_w[setting]
+    for f, (lo, hi) in enumerate(COUNTER_RANGES):
+        X[:, 2 + f] = r.uniform(lo, hi, size=len(setting))
+    return X
+
+
+def predictor_params(cfg_id: int, grid: Grid, seed: int = 0, hidden: int = 64) -> dict:
+    """Random weights of the 7 -> 64 -> 64 -> 1 predictor (He-uniform hidden layers, small
+    output layer, output bias 0.75) and the centring/scaling of each feature from the mean and
+    standard deviation of the ranges it is drawn from.  No trained weights exist."""
+    r = rng(cfg_id, S_PRED, seed)
+    ranges = [(grid.cpu_w.min(), grid.cpu_w.max()), (grid.gpu_w.min(), grid.gpu_w.max())] + list(COUNTER_RANGES)
+    mu = np.array([(lo + hi) / 2 for lo, hi in ranges])
+    sd = np.array([(hi - lo) / np.sqrt(12.0) for lo, hi in ranges])
+    b1w, b2w = np.sqrt(6.0 / 7), np.sqrt(6.0 / hidden)
+    p = dict(mu=mu, rs=1.0 / sd,
+             W1=r.uniform(-b1w, b1w, (hidden, 7)), b1=r.uniform(-0.1, 0.1, hidden),
+             W2=r.uniform(-b2w, b2w, (hidden, hidden)), b2=r.uniform(-0.1, 0.1, hidden),
+             w3=r.uniform(-0.05, 0.05, hidden), b3=np.array([0.75]))
+    return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in p.items()}

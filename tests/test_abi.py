@@ -44,3 +44,6 @@ def test_host_only_calls():
     # null context is rejected before any device work
     assert L.open_foldin(None, None, 0, 32, 0, None, None, None, 0.05, 1, None, None) == native.OPEN_E_INVALID
     assert L.open_last_error(None) == b"null context"
+    assert L.open_perf_predict(None, None, 0, None, None, None, None, None, None, None, None,
+                               None) == native.OPEN_E_INVALID
+    assert L.open_phase_detect(None, None, 0, 0, 0, 60.0, 25, None) == native.OPEN_E_INVALID
