@@ -270,6 +270,47 @@ def predictor_leg(ctx, rows, grid, steps, warmup, log):
                          "bf16_mfma_tflops": round(tf, 2), "bf16_mfma_frac": round(tf / PEAK_BF16_TFLOPS, 4)}}
 
 
+def ncf_leg(ctx, steps, warmup, log):
+    """NCF fold-in (SELU network, embedding learned by 30 gradient steps per new app) for
+    65,536 new apps with 4-24 observed settings each: apps per second.  Algorithmic work per
+    observed entry and step: forward 2 (32*64 + 64*64 + 64) flop, backward 2 (64 + 64*64)
+    flop, plus 2*32*64 flop per app and step for the embedding layer both ways."""
+    import numpy as np
+    import torch
+
+    from paper_2508_07605_amd import native, synth
+
+    c = synth.NCF
+    grid = synth.grid_of("foldin")
+    m = 65_536
+    rows = synth.draw_rows(3, grid, m, ("uniform", 4, 24), seed=0)
+    p = synth.ncf_params(3, grid.n)
+    S = torch.from_numpy(p.pop("S")).cuda()
+    dp = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
+    drp, dcol, dval = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (rows.row_ptr, rows.col, rows.val))
+    E = torch.empty((m, 32), dtype=torch.float32, device=S.device)
+    L = torch.empty(m, dtype=torch.float32, device=S.device)
+    reps = max(1, steps // 4)
+    for _ in range(max(1, warmup // 2)):
+        native.open_ncf_foldin(ctx, S, dp, drp, dcol, dval, c["steps"], c["eta"], c["mu"], E_out=E, loss_out=L)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        native.open_ncf_foldin(ctx, S, dp, drp, dcol, dval, c["steps"], c["eta"], c["mu"], E_out=E, loss_out=L)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nnz = float(rows.nnz)
+    flops = c["steps"] * (nnz * 2 * (32 * 64 + 64 * 64 + 64 + 64 + 64 * 64) + m * 2 * 2 * 32 * 64)
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": "NCF fold-in: %d new apps x 480 settings, 4-24 observed, embedding 32, SELU 64-64, "
+                        "%d gradient steps" % (m, c["steps"]),
+            "apps_per_s": m / (ms * 1e-3), "ms_per_call": ms, "mean_final_loss": float(L.mean().item()),
+            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops}}
+
+
 def refit_leg(ctx, state, log):
     """Warm-started refit: 50k new apps (4-24 observed each) arrive at the fitted 200k x 480
     matrix; fold-in alone vs fold-in + 2 ALS sweeps on the union, timed, with the RMSE of both
@@ -391,6 +432,7 @@ def main():
     ap.add_argument("--no-fit", action="store_true", help="skip the ALS fit leg")
     ap.add_argument("--no-phase", action="store_true", help="skip the Alg. 1 phase-detection leg")
     ap.add_argument("--no-predictor", action="store_true", help="skip the offline performance predictor leg")
+    ap.add_argument("--no-ncf", action="store_true", help="skip the NCF fold-in leg")
     ap.add_argument("--fit-sweeps", type=int, default=3, help="timed ALS sweeps in the fit leg")
     ap.add_argument("--surrogate-epochs", type=float, default=2.0,
                     help="training epochs over the 2M ALS fold-in targets (batch 4096, Adam 1e-3)")
@@ -540,6 +582,11 @@ def main():
         log("offline predictor %.3e runs/s, %.0f GB/s, %.1f TFLOP/s" % (
             out["perf_predictor"]["runs_per_s"], out["perf_predictor"]["roofline"]["achieved"],
             out["perf_predictor"]["roofline"]["bf16_mfma_tflops"]))
+    if not args.no_ncf:
+        out["ncf_foldin"] = ncf_leg(ctx, args.steps, args.warmup, log)
+        log("NCF fold-in %.3e apps/s (%.3f ms), %.1f TFLOP/s" % (
+            out["ncf_foldin"]["apps_per_s"], out["ncf_foldin"]["ms_per_call"],
+            out["ncf_foldin"]["roofline"]["achieved"]))
     if not args.no_fit:
         fit_state, out["fit"] = fit_leg(args, ctx, log)
         out["refit"] = refit_leg(ctx, fit_state, log)

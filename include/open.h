@@ -278,6 +278,29 @@ open_status open_perf_predict(open_ctx *ctx, const float *X, int64_t n_runs, con
                               const float *W1, const float *b1, const float *W2, const float *b2, const float *w3,
                               const float *b3, float *y);
 
+/*
+ * Neural collaborative filtering fold-in (Section III-B.1 model; Section III-B.2, the new
+ * application's missing entries are imputed by the CF model).  The model scores application
+ * embedding e against setting embedding s_j:
+ *   y(e, s_j) = w3 . SELU(W2 SELU(W1 [e; s_j] + b1) + b2) + b3,
+ * SELU(z) = lambda (z if z > 0 else alpha (exp(z) - 1)), alpha = 1.6732632..., lambda =
+ * 1.0507009....  For each CSR row i (observed settings col, values val) the embedding E_out[i]
+ * is learned with S and the network fixed: `steps` steps of gradient descent from e = 0 with
+ * step eta on L(e) = (1/q) sum_j (y(e, s_j) - r_ij)^2 + mu |e|^2 (q = entries of the row).
+ *   S        device float32[n*d] setting embeddings, d = 32 (else OPEN_E_UNSUPPORTED)
+ *   W1       device float32[64*2d] row-major (unit major; the first d inputs are e); b1[64]
+ *   W2       device float32[64*64]; b2[64]; w3[64]; b3[1]
+ *   E_out    device float32[m*d], written; loss_out device float32[m] or NULL: L(e) at the
+ *            returned e; row_status device int32[m] or NULL.
+ * Rows with no entry (status 1), a column outside [0, n) (status 5) or a non-finite value
+ * (status 3) keep e = 0 and loss 0.  Float32 arithmetic.  OPEN_E_INVALID for n < 1, m < 0,
+ * steps < 0, NaN eta or mu, or a null pointer.  Asynchronous on the context's stream.
+ */
+open_status open_ncf_foldin(open_ctx *ctx, const float *S, int32_t n, int32_t d, const float *W1, const float *b1,
+                            const float *W2, const float *b2, const float *w3, const float *b3, int64_t m,
+                            const int64_t *row_ptr, const int32_t *col, const float *val, int32_t steps, float eta,
+                            float mu, float *E_out, float *loss_out, int32_t *row_status);
+
 #ifdef __cplusplus
 }
 #endif

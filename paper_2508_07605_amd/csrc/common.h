@@ -112,7 +112,7 @@ struct open_ctx {
   // grow-only device workspaces, indexed by purpose
   enum {
     WS_HIST, WS_CLS, WS_LIST, WS_CSC_PTR, WS_CSC_IDX, WS_CSC_VAL, WS_RED, WS_SPLIT, WS_MISC, WS_FLAG, WS_OBJ,
-    WS_PRED, WS_SPLIT_START, WS_SPLIT_PART, WS_SPLIT_FLAG, WS_COUNT
+    WS_PRED, WS_SPLIT_START, WS_SPLIT_PART, WS_SPLIT_FLAG, WS_NCF, WS_COUNT
   };
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};

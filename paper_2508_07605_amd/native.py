@@ -36,6 +36,8 @@ SIGNATURES = {
     "open_foldin_graph": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_phase_detect": (_I32, [_P, _P, _I64, _I64, _I64, _F32, _I32, _P]),
     "open_perf_predict": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "open_ncf_foldin": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _I32, _F32, _F32, _P,
+                               _P, _P]),
     "open_refit": (_I32, [_P, _I64, _I64, _I32, _I32, _P, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
     "open_tune_info": (_I32, [_I32, _P, _P, _I32]),
     "open_tune_get": (_I32, [_P, _I32, _P, _I32]),
@@ -214,6 +216,25 @@ def open_perf_predict(ctx, X, params, y=None):
     ctx.check(lib().open_perf_predict(ctx.handle, _dev(X, torch.float32, "X", n * 7), n, *ptrs,
                                       _dev(y, torch.float32, "y", n)))
     return y
+
+
+def open_ncf_foldin(ctx, S, params, row_ptr, col, val, steps, eta, mu, E_out=None, loss_out=None,
+                    row_status=None):
+    """NCF fold-in of the CSR rows against setting embeddings S (device float32 [n, 32]);
+    params holds device float32 W1[64, 64], b1[64], W2[64, 64], b2[64], w3[64], b3[1]."""
+    n, d = S.shape
+    m = row_ptr.numel() - 1
+    if E_out is None:
+        E_out = torch.empty((m, d), dtype=torch.float32, device=S.device)
+    sizes = {"W1": 64 * 2 * d, "b1": 64, "W2": 4096, "b2": 64, "w3": 64, "b3": 1}
+    ptrs = [_dev(params[name], torch.float32, name, cnt) for name, cnt in sizes.items()]
+    ctx.check(lib().open_ncf_foldin(ctx.handle, _dev(S, torch.float32, "S", n * d), n, d, *ptrs, m,
+                                    _dev(row_ptr, torch.int64, "row_ptr", m + 1), _dev(col, torch.int32, "col"),
+                                    _dev(val, torch.float32, "val"), int(steps), float(eta), float(mu),
+                                    _dev(E_out, torch.float32, "E_out", m * d),
+                                    _dev(loss_out, torch.float32, "loss_out", m),
+                                    _dev(row_status, torch.int32, "row_status", m)))
+    return E_out
 
 
 def open_tune_info(k):

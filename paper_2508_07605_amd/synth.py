@@ -22,7 +22,7 @@ import numpy as np
 SEED_TAG = 20250811
 
 # independent random streams per configuration
-S_APPS, S_COUNTS, S_SETS, S_NOISE, S_INIT, S_MLP, S_REF, S_EVAL, S_POWER, S_COUNTERS, S_PRED = range(11)
+S_APPS, S_COUNTS, S_SETS, S_NOISE, S_INIT, S_MLP, S_REF, S_EVAL, S_POWER, S_COUNTERS, S_PRED, S_NCF = range(12)
 
 
 def rng(cfg_id: int, stream: int, seed: int = 0) -> np.random.Generator:
@@ -313,4 +313,21 @@ def predictor_params(cfg_id: int, grid: Grid, seed: int = 0, hidden: int = 64) -
              W1=r.uniform(-b1w, b1w, (hidden, 7)), b1=r.uniform(-0.1, 0.1, hidden),
              W2=r.uniform(-b2w, b2w, (hidden, hidden)), b2=r.uniform(-0.1, 0.1, hidden),
              w3=r.uniform(-0.05, 0.05, hidden), b3=np.array([0.75]))
+    return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in p.items()}
+
+
+# ----------------------------------------------------------------------------- NCF
+NCF = dict(d=32, hidden=64, steps=30, eta=0.5, mu=1e-3)
+
+
+def ncf_params(cfg_id: int, n: int, seed: int = 0, d: int = 32, hidden: int = 64) -> dict:
+    """Random NCF weights (no trained model exists): setting embeddings S (n x d) ~ N(0, 1),
+    LeCun-normal hidden layers (std 1/sqrt(fan_in), the SELU initialisation), zero hidden
+    biases, output weights ~ N(0, 1/hidden) and output bias 0.75 (the middle of the normalized
+    performance range)."""
+    r = rng(cfg_id, S_NCF, seed)
+    p = dict(S=r.standard_normal((n, d)),
+             W1=r.standard_normal((hidden, 2 * d)) / np.sqrt(2 * d), b1=np.zeros(hidden),
+             W2=r.standard_normal((hidden, hidden)) / np.sqrt(hidden), b2=np.zeros(hidden),
+             w3=r.standard_normal(hidden) / np.sqrt(hidden), b3=np.array([0.75]))
     return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in p.items()}

@@ -1,0 +1,128 @@
+"""GPU parity of the NCF fold-in (Section III-B.1 model, gradient-descent embedding of new
+applications) against the FP64 oracle, through the C ABI.
+
+SELU's derivative jumps at 0 (lambda on the right, lambda * alpha on the left), so a
+pre-activation that lands within rounding distance of 0 somewhere along a row's 30 steps can
+take the other branch in float32 than in float64; the two trajectories then part by a small
+finite amount and both are valid gradient-descent runs.  The checks are therefore:
+  * statuses equal;
+  * per row e = |E - E_ref| / |E_ref|: 99 % of rows within 1e-4 (float32 forward and backward
+    passes over 30 contracting steps), every row within 5e-2;
+  * what does not depend on the branch taken: the loss the oracle evaluates at the GPU's
+    embedding is within 1e-3 (relative) of the oracle's own final loss, and the loss the GPU
+    reports equals the oracle's evaluation at the GPU's embedding within 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ncf
+from paper_2508_07605_amd import native, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+C = synth.NCF
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def model(n, seed=0):
+    p = synth.ncf_params(3, n, seed=seed)
+    S = p.pop("S")
+    return S, p
+
+
+def run(ctx, S, p, rp, col, val, steps=C["steps"], eta=C["eta"], mu=C["mu"]):
+    m = len(rp) - 1
+    L = torch.full((m,), -1.0, device="cuda")
+    st = torch.full((m,), -7, dtype=torch.int32, device="cuda")
+    E = native.open_ncf_foldin(ctx, dev(S), {k: dev(v) for k, v in p.items()}, dev(rp), dev(col), dev(val), steps,
+                               eta, mu, loss_out=L, row_status=st)
+    torch.cuda.synchronize()
+    return E.cpu().numpy().astype(np.float64), L.cpu().numpy().astype(np.float64), st.cpu().numpy()
+
+
+def compare(name, E, L, st, ref, S, p, rp, col, val, rows=None):
+    Er, Lr, str_ = ref
+    assert np.array_equal(st, str_)
+    nrm = np.maximum(np.linalg.norm(Er, axis=1), 1e-3)
+    e = np.linalg.norm(E - Er, axis=1) / nrm
+    Lg = ncf.loss_rows(rp, col, val, S, p, C["mu"], E, rows=rows)  # oracle loss at the GPU embedding
+    den = np.maximum(np.abs(Lr), 1e-3)
+    reach = (Lg - Lr) / den
+    evalerr = np.abs(L - Lg) / np.maximum(np.abs(Lg), 1e-3)
+    print("%s: rows %d  e p50 %.2e p99 %.2e max %.2e  loss reached %+.2e  loss eval %.2e"
+          % (name, len(E), np.median(e), np.percentile(e, 99), e.max(), np.abs(reach).max(), evalerr.max()))
+    assert np.percentile(e, 99) <= TOL and e.max() <= 5e-2
+    assert np.abs(reach).max() <= 1e-3
+    assert evalerr.max() <= TOL
+
+
+def test_parity_mixed_counts(ctx):
+    # the fold-in count range plus very short and longer rows
+    grid = synth.grid_of("foldin")
+    S, p = model(grid.n)
+    rows = synth.draw_rows(3, grid, 700, ("uniform", 1, 70), seed=21)
+    E, L, st = run(ctx, S, p, rows.row_ptr, rows.col, rows.val)
+    compare("ncf mixed", E, L, st, ncf.foldin(rows.row_ptr, rows.col, rows.val, S, p, C["steps"], C["eta"], C["mu"]),
+            S, p, rows.row_ptr, rows.col, rows.val)
+
+
+def test_step_counts_and_statuses(ctx):
+    grid = synth.grid_of("foldin")
+    S, p = model(grid.n, seed=1)
+    rows = synth.draw_rows(3, grid, 64, ("uniform", 4, 24), seed=22)
+    for steps in (0, 1, 7):
+        E, L, st = run(ctx, S, p, rows.row_ptr, rows.col, rows.val, steps=steps)
+        compare("ncf steps=%d" % steps, E, L, st,
+                ncf.foldin(rows.row_ptr, rows.col, rows.val, S, p, steps, C["eta"], C["mu"]), S, p, rows.row_ptr,
+                rows.col, rows.val)
+    rp = np.array([0, 0, 2, 4, 6], dtype=np.int64)
+    col = np.array([1, 2, 3, grid.n, 5, 6], dtype=np.int32)
+    val = np.array([0.5, 0.6, 0.7, 0.8, np.nan, 0.9], dtype=np.float32)
+    E, L, st = run(ctx, S, p, rp, col, val, steps=10)
+    assert st.tolist() == [1, 0, 5, 3]
+    assert (E[[0, 2, 3]] == 0).all() and (L[[0, 2, 3]] == 0).all()
+    compare("ncf status rows", E, L, st, ncf.foldin(rp, col, val, S, p, 10, C["eta"], C["mu"]), S, p, rp, col, val)
+
+
+def test_invalid_arguments(ctx):
+    S, p = model(8)
+    rp = dev(np.array([0, 1], dtype=np.int64))
+    col = dev(np.array([0], dtype=np.int32))
+    val = dev(np.array([0.5], dtype=np.float32))
+    with pytest.raises(native.OpenError):
+        native.open_ncf_foldin(ctx, dev(S), {k: dev(v) for k, v in p.items()}, rp, col, val, -1, 0.5, 1e-3)
+    with pytest.raises(native.OpenError):  # embedding width other than 32
+        native.open_ncf_foldin(ctx, dev(S[:, :16]), {k: dev(v) for k, v in p.items()}, rp, col, val, 5, 0.5, 1e-3)
+
+
+def test_deterministic(ctx):
+    grid = synth.grid_of("foldin")
+    S, p = model(grid.n, seed=2)
+    rows = synth.draw_rows(3, grid, 3000, ("uniform", 4, 24), seed=23)
+    a = run(ctx, S, p, rows.row_ptr, rows.col, rows.val)
+    b = run(ctx, S, p, rows.row_ptr, rows.col, rows.val)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_benchmark_workload_sampled(ctx):
+    # the benchmark's NCF workload (65,536 new apps, 4-24 observed each) in its launch
+    # configuration; the oracle recomputes a seeded sample of rows
+    grid = synth.grid_of("foldin")
+    S, p = model(grid.n)
+    rows = synth.draw_rows(3, grid, 65_536, ("uniform", 4, 24), seed=0)
+    E, L, st = run(ctx, S, p, rows.row_ptr, rows.col, rows.val)
+    assert (st == 0).all() and np.isfinite(E).all()
+    sample = np.sort(np.random.default_rng(4).choice(rows.m, size=300, replace=False))
+    ref = ncf.foldin(rows.row_ptr, rows.col, rows.val, S, p, C["steps"], C["eta"], C["mu"], rows=sample)
+    compare("ncf 65536-row sample", E[sample], L[sample], st[sample], ref, S, p, rows.row_ptr, rows.col, rows.val,
+            rows=sample)
