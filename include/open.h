@@ -294,7 +294,8 @@ open_status open_perf_predict(open_ctx *ctx, const float *X, int64_t n_runs, con
  *            returned e; row_status device int32[m] or NULL.
  * Rows with no entry (status 1), a column outside [0, n) (status 5) or a non-finite value
  * (status 3) keep e = 0 and loss 0.  Float32 arithmetic.  OPEN_E_INVALID for n < 1, m < 0,
- * steps < 0, NaN eta or mu, or a null pointer.  Asynchronous on the context's stream.
+ * steps outside [0, 100000], NaN eta or mu, or a null pointer.  Asynchronous on the context's
+ * stream.
  */
 open_status open_ncf_foldin(open_ctx *ctx, const float *S, int32_t n, int32_t d, const float *W1, const float *b1,
                             const float *W2, const float *b2, const float *w3, const float *b3, int64_t m,

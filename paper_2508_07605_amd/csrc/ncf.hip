@@ -17,6 +17,7 @@
 namespace openk {
 
 constexpr int kNcfD = 32, kNcfH = 64;
+constexpr int kNcfMaxSteps = 100000;  // bounds a launch's run time
 constexpr int kNcfW2P = kNcfH + 1, kNcfW1P = kNcfD + 1;
 constexpr float kSeluAlpha = 1.6732632423543772f, kSeluLambda = 1.0507009873554805f;
 
@@ -154,7 +155,7 @@ extern "C" open_status open_ncf_foldin(open_ctx *ctx, const float *S, int32_t n,
                                        float *loss_out, int32_t *row_status) {
   if (!ctx) return OPEN_E_INVALID;
   if (d != kNcfD) return fail(ctx, OPEN_E_UNSUPPORTED, "embedding width must be 32");
-  if (n < 1 || m < 0 || steps < 0 || !(eta == eta) || !(mu == mu))
+  if (n < 1 || m < 0 || steps < 0 || steps > kNcfMaxSteps || !(eta == eta) || !(mu == mu))
     return fail(ctx, OPEN_E_INVALID, "bad sizes, steps, eta or mu");
   if (m == 0) return OPEN_OK;
   if (!S || !W1 || !b1 || !W2 || !b2 || !w3 || !b3 || !row_ptr || !col || !val || !E_out)

@@ -101,6 +101,8 @@ def test_invalid_arguments(ctx):
     val = dev(np.array([0.5], dtype=np.float32))
     with pytest.raises(native.OpenError):
         native.open_ncf_foldin(ctx, dev(S), {k: dev(v) for k, v in p.items()}, rp, col, val, -1, 0.5, 1e-3)
+    with pytest.raises(native.OpenError):  # more steps than one launch is allowed to run
+        native.open_ncf_foldin(ctx, dev(S), {k: dev(v) for k, v in p.items()}, rp, col, val, 100_001, 0.5, 1e-3)
     with pytest.raises(native.OpenError):  # embedding width other than 32
         native.open_ncf_foldin(ctx, dev(S[:, :16]), {k: dev(v) for k, v in p.items()}, rp, col, val, 5, 0.5, 1e-3)
 
