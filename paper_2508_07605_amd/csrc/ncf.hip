@@ -7,18 +7,12 @@
 // The setting half of the first layer is the same for every application and every step, so
 // a table C[j] = W1[:, d:] s_j + b1 (n x 64) is built once per call; a step then needs only
 // a = W1[:, :d] e, and a setting's first pre-activation is a + C[j].
-//
-// One wavefront per application; lane l owns hidden unit l of both layers and lane k < 32 owns
-// e_k.  Activations move between lanes with readlane (the index is a compile-time constant),
-// W2 and the embedding half of W1 sit in LDS with an odd pitch so that both a row and a column
-// are read without bank conflicts, and each lane keeps its row of W1[:, :d] in registers.
 #include "common.h"
 
 namespace openk {
 
 constexpr int kNcfD = 32, kNcfH = 64;
 constexpr int kNcfMaxSteps = 100000;  // bounds a launch's run time
-constexpr int kNcfW2P = kNcfH + 1, kNcfW1P = kNcfD + 1;
 constexpr float kSeluAlpha = 1.6732632423543772f, kSeluLambda = 1.0507009873554805f;
 
 __device__ __forceinline__ void selu_and_grad(float z, float &h, float &dh) {
@@ -49,30 +43,79 @@ __global__ void k_ncf_table(const float *__restrict__ S, int n, const float *__r
   C[t] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_ncf_foldin(int64_t m, const int64_t *__restrict__ ptr,
+// Observation tiles on FP32 MFMA (v_mfma_f32_32x32x2f32).  One wavefront per application,
+// its observations in tiles of 32 along the MFMA columns (lane j = l % 32 is observation j of
+// the tile, g = l / 32 the half).  Every 32 x 32 result holds, in register v of lane (j, g),
+// row 8 (v/4) + 4 g + v%4 of its block; hidden unit U(b, v, g) = 32 b + that row, embedding
+// index K(v, g) = that row.  Each product's contraction index is ordered so that its B operand
+// is a register the lane already holds:
+//   a   = W1e e         (64 x 32):  step s, half g <-> embedding K(s, g)   (e kept as e[K(v, g)])
+//   Z2  = W2 H1         (64 x 64):  step t, half g <-> hidden U(t/16, t%16, g)
+//   dH1 = W2^T dZ2      (64 x 64):  step t, half g <-> layer-2 unit U(t/16, t%16, g)
+//   DE  = W1e^T dZ1     (32 x 64):  step t, half g <-> hidden U(t/16, t%16, g)
+// so activations never move between lanes.  The A operands depend on the lane only and sit in
+// LDS once per block, slot-major so that consecutive lanes read consecutive 16-byte words.
+// DE's columns (observations) are summed across the 32 lanes of each half.
+constexpr int kNcfTA = 0, kNcfTF = 8, kNcfTB = 24, kNcfTE = 40, kNcfTW3 = 48, kNcfTB2 = 56, kNcfTSlots = 64;
+
+__device__ __forceinline__ f16 mfma32(float a, float b, f16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int ncf_row(int v, int g) { return 8 * (v >> 2) + 4 * g + (v & 3); }
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ncf_foldin(int64_t m, const int64_t *__restrict__ ptr,
                                                     const int32_t *__restrict__ col, const float *__restrict__ val,
                                                     int n, const float *__restrict__ C, const float *__restrict__ W1,
                                                     const float *__restrict__ W2, const float *__restrict__ b2,
                                                     const float *__restrict__ w3, const float *__restrict__ b3,
                                                     int steps, float eta, float mu, float *__restrict__ E,
                                                     float *__restrict__ Lout, int32_t *__restrict__ status) {
-  __shared__ float w2s[kNcfH * kNcfW2P];  // W2[m][k] at m * 65 + k
-  __shared__ float w1s[kNcfH * kNcfW1P];  // W1[l][k], k < d, at l * 33 + k
-  for (int q = threadIdx.x; q < kNcfH * kNcfH; q += blockDim.x) w2s[(q / kNcfH) * kNcfW2P + q % kNcfH] = W2[q];
-  for (int q = threadIdx.x; q < kNcfH * kNcfD; q += blockDim.x)
-    w1s[(q / kNcfD) * kNcfW1P + q % kNcfD] = W1[(q / kNcfD) * 2 * kNcfD + q % kNcfD];
+  // tab[slot][lane]: per-lane operands, four floats per slot
+  __shared__ f4 tab[kNcfTSlots][kWave];
+  if (threadIdx.x < kWave) {
+    const int l = threadIdx.x, j = l & 31, g = l >> 5;
+    float *t = nullptr;
+    // a = W1e e: A[b][s] = W1e[32 b + j][K(s, g)]
+    for (int b = 0; b < 2; ++b)
+      for (int s = 0; s < 16; ++s) {
+        t = reinterpret_cast<float *>(&tab[kNcfTA + (16 * b + s) / 4][l]);
+        t[s & 3] = W1[(32 * b + j) * 2 * kNcfD + ncf_row(s, g)];
+      }
+    // Z2 = W2 H1: A[ob][t] = W2[32 ob + j][U(t)], and dH1 = W2^T dZ2: A[b][t] = W2[U(t)][32 b + j]
+    for (int ob = 0; ob < 2; ++ob)
+      for (int q = 0; q < 32; ++q) {
+        const int u = 32 * (q >> 4) + ncf_row(q & 15, g);
+        reinterpret_cast<float *>(&tab[kNcfTF + (32 * ob + q) / 4][l])[q & 3] = W2[(32 * ob + j) * kNcfH + u];
+        reinterpret_cast<float *>(&tab[kNcfTB + (32 * ob + q) / 4][l])[q & 3] = W2[u * kNcfH + 32 * ob + j];
+      }
+    // DE = W1e^T dZ1: A[t] = W1e[U(t)][j]
+    for (int q = 0; q < 32; ++q) {
+      const int u = 32 * (q >> 4) + ncf_row(q & 15, g);
+      reinterpret_cast<float *>(&tab[kNcfTE + q / 4][l])[q & 3] = W1[u * 2 * kNcfD + j];
+    }
+    // w3 and b2 at this lane's rows
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 16; ++v) {
+        const int u = 32 * b + ncf_row(v, g);
+        reinterpret_cast<float *>(&tab[kNcfTW3 + (16 * b + v) / 4][l])[v & 3] = w3[u];
+        reinterpret_cast<float *>(&tab[kNcfTB2 + (16 * b + v) / 4][l])[v & 3] = b2[u];
+      }
+  }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  float w1r[kNcfD];  // this lane's row of W1[:, :d]
-#pragma unroll
-  for (int k = 0; k < kNcfD; ++k) w1r[k] = w1s[lane * kNcfW1P + k];
-  const float b2l = b2[lane], w3l = w3[lane], bias3 = b3[0];
+  const int lane = threadIdx.x & 63, jl = lane & 31, g = lane >> 5;
+  const float bias3 = b3[0];
+  // The table reads go through an offset the compiler cannot see through, renewed every tile,
+  // so that it reads the operands from LDS where they are used instead of holding all 256 in
+  // registers.
+  int toff = 0;
+  auto T = [&](int slot, int q) {
+    return reinterpret_cast<const float *>(&tab[0][0])[((slot + q / 4) * kWave + lane + toff) * 4 + (q & 3)];
+  };
 
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < m; i += nw) {
     const int64_t beg = ptr[i], end = ptr[i + 1];
     const int q = (int)(end - beg);
-    // row checks: empty, setting index out of range, non-finite value
     int st = q <= 0 ? 1 : 0;
     if (st == 0) {
       bool bad_idx = false, bad_val = false;
@@ -84,59 +127,97 @@ __global__ __launch_bounds__(256) void k_ncf_foldin(int64_t m, const int64_t *__
       if (__ballot(bad_idx)) st = 5;
       else if (__ballot(bad_val)) st = 3;
     }
-    float e = 0.f;  // e_lane for lanes < 32
+    float e[16];  // e[v] = embedding K(v, g)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) e[v] = 0.f;
     float lossv = 0.f;
     if (st == 0) {
       const float inv_q = 1.f / (float)q;
       for (int it = 0; it <= steps; ++it) {
-        // a_l = sum_k W1[l][k] e_k
-        float a = 0.f;
+        // a at this lane's hidden units
+        asm volatile("" : "+v"(toff));
+        f16 a[2] = {};
 #pragma unroll
-        for (int k = 0; k < kNcfD; ++k)
-          a = __builtin_fmaf(w1r[k], __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, e), k)),
-                             a);
-        float g = 0.f, sq = 0.f;
-        for (int64_t t = beg; t < end; ++t) {
-          const int j = col[t];
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int s2 = 0; s2 < 16; ++s2) a[b] = mfma32(T(kNcfTA, 16 * b + s2), e[s2], a[b]);
+        f16 de = {};
+        float sq = 0.f;
+        for (int64_t t0 = beg; t0 < end; t0 += 32) {
+          asm volatile("" : "+v"(toff));
+          const bool valid = t0 + jl < end;
+          const int64_t t = valid ? t0 + jl : beg;
+          const float* crow = C + (int64_t)col[t] * kNcfH;
           const float r = val[t];
-          float h1, d1;
-          selu_and_grad(a + C[(int64_t)j * kNcfH + lane], h1, d1);
-          float z2 = b2l;
+          // forward: Z2 = b2 + W2 SELU(a + c)
+          f16 z2[2];
 #pragma unroll
-          for (int k = 0; k < kNcfH; ++k)
-            z2 = __builtin_fmaf(w2s[lane * kNcfW2P + k],
-                                __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, h1), k)), z2);
-          float h2, d2;
-          selu_and_grad(z2, h2, d2);
-          const float y = wave_sum_f(w3l * h2) + bias3;
-          const float res = y - r;
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) z2[b][v] = T(kNcfTB2, 16 * b + v);
+          float cz[32];
+#pragma unroll
+          for (int q2 = 0; q2 < 32; ++q2) cz[q2] = crow[32 * (q2 >> 4) + ncf_row(q2 & 15, g)];
+#pragma unroll
+          for (int q2 = 0; q2 < 32; ++q2) {
+            float h1;
+            selu_and_grad(a[q2 >> 4][q2 & 15] + cz[q2], h1, cz[q2]);  // cz now holds SELU'(z1)
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob) z2[ob] = mfma32(T(kNcfTF, 32 * ob + q2), h1, z2[ob]);
+          }
+          // output and residual of observation jl (both halves hold half of the sum)
+          float yp = 0.f;
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              float h2, d2;
+              selu_and_grad(z2[b][v], h2, d2);
+              yp = __builtin_fmaf(T(kNcfTW3, 16 * b + v), h2, yp);
+            }
+          const float y = yp + __shfl_xor(yp, 32, kWave) + bias3;
+          const float res = valid ? y - r : 0.f;
           sq = __builtin_fmaf(res, res, sq);
           if (it == steps) continue;  // the last pass only evaluates the loss
-          const float dz2 = 2.f * res * inv_q * w3l * d2;
-          float dh1 = 0.f;
+          // backward: dH1 = W2^T dZ2, dZ2 = (2 res / q) w3 SELU'(z2)
+          const float dy = 2.f * res * inv_q;
+          f16 dh1[2] = {};
 #pragma unroll
-          for (int mm = 0; mm < kNcfH; ++mm)
-            dh1 = __builtin_fmaf(w2s[mm * kNcfW2P + lane],
-                                 __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dz2), mm)),
-                                 dh1);
-          g = __builtin_fmaf(dh1, d1, g);
+          for (int q2 = 0; q2 < 32; ++q2) {
+            float h2, d2;
+            selu_and_grad(z2[q2 >> 4][q2 & 15], h2, d2);
+            const float dz2 = dy * T(kNcfTW3, q2) * d2;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) dh1[b] = mfma32(T(kNcfTB, 32 * b + q2), dz2, dh1[b]);
+          }
+          // DE += W1e^T (dH1 * SELU'(a + c))
+#pragma unroll
+          for (int q2 = 0; q2 < 32; ++q2) de = mfma32(T(kNcfTE, q2), dh1[q2 >> 4][q2 & 15] * cz[q2], de);
         }
         if (it == steps) {
-          const float ee = lane < kNcfD ? e * e : 0.f;
-          lossv = sq * inv_q + mu * wave_sum_f(ee);
+          float ee = 0.f;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) ee = __builtin_fmaf(e[v], e[v], ee);
+          // sq: one value per observation in each half; ee: each half holds its 16 indices
+          const float sqt = wave_sum_f(g == 0 ? sq : 0.f);
+          const float eet = __shfl(ee, 0, kWave) + __shfl(ee, 32, kWave);
+          lossv = sqt * inv_q + mu * eet;
           break;
         }
-        // de_k = sum_l W1[l][k] g_l + 2 mu e_k, on lanes k < d
-        float de = 0.f;
-        const int kk = lane < kNcfD ? lane : 0;
+        // sum DE over the observation columns (the 32 lanes of each half), then the step
 #pragma unroll
-        for (int l = 0; l < kNcfH; ++l)
-          de = __builtin_fmaf(w1s[l * kNcfW1P + kk],
-                              __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, g), l)), de);
-        if (lane < kNcfD) e -= eta * (de + 2.f * mu * e);
+        for (int v = 0; v < 16; ++v) {
+          float x = de[v];
+#pragma unroll
+          for (int off = 1; off < 32; off <<= 1) x += __shfl_xor(x, off, kWave);
+          e[v] -= eta * (x + 2.f * mu * e[v]);
+        }
       }
     }
-    if (lane < kNcfD) E[i * kNcfD + lane] = e;
+    if (jl == 0) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) E[i * kNcfD + ncf_row(v, g)] = e[v];
+    }
     if (lane == 0) {
       if (Lout) Lout[i] = st == 0 ? lossv : 0.f;
       if (status) status[i] = st;
