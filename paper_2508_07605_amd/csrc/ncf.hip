@@ -43,9 +43,10 @@ __global__ void k_ncf_table(const float *__restrict__ S, int n, const float *__r
   C[t] = acc;
 }
 
-// Observation tiles on FP32 MFMA (v_mfma_f32_32x32x2f32).  One wavefront per application,
-// its observations in tiles of 32 along the MFMA columns (lane j = l % 32 is observation j of
-// the tile, g = l / 32 the half).  Every 32 x 32 result holds, in register v of lane (j, g),
+// Observation tiles on FP32 MFMA (v_mfma_f32_32x32x2f32).  One wavefront per two applications:
+// the 32 MFMA columns hold 16 observations of each (lane j = l % 32 is column j, g = l / 32 the
+// half); the MFMA keeps columns apart, so each column simply carries its own application's
+// embedding.  Every 32 x 32 result holds, in register v of lane (j, g),
 // row 8 (v/4) + 4 g + v%4 of its block; hidden unit U(b, v, g) = 32 b + that row, embedding
 // index K(v, g) = that row.  Each product's contraction index is ordered so that its B operand
 // is a register the lane already holds:
@@ -55,7 +56,7 @@ __global__ void k_ncf_table(const float *__restrict__ S, int n, const float *__r
 //   DE  = W1e^T dZ1     (32 x 64):  step t, half g <-> hidden U(t/16, t%16, g)
 // so activations never move between lanes.  The A operands depend on the lane only and sit in
 // LDS once per block, slot-major so that consecutive lanes read consecutive 16-byte words.
-// DE's columns (observations) are summed across the 32 lanes of each half.
+// DE's columns (observations) are summed across each application's 16 lanes of a half.
 constexpr int kNcfTA = 0, kNcfTF = 8, kNcfTB = 24, kNcfTE = 40, kNcfTW3 = 48, kNcfTB2 = 56, kNcfTSlots = 64;
 
 __device__ __forceinline__ f16 mfma32(float a, float b, f16 c) {
@@ -112,27 +113,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     return reinterpret_cast<const float *>(&tab[0][0])[((slot + q / 4) * kWave + lane + toff) * 4 + (q & 3)];
   };
 
+  // two applications per wavefront: columns 0..15 of every tile belong to the first, 16..31
+  // to the second (observations in tiles of 16 per application)
+  const int half = jl >> 4, jc = jl & 15;
+  const uint64_t appmask = 0x0000ffff0000ffffull << (16 * half);
+  const int64_t npairs = (m + 1) >> 1;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < m; i += nw) {
-    const int64_t beg = ptr[i], end = ptr[i + 1];
+  for (int64_t pr = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); pr < npairs; pr += nw) {
+    const int64_t i = 2 * pr + half;  // this lane's application
+    const bool has = i < m;
+    const int64_t beg = has ? ptr[i] : 0, end = has ? ptr[i + 1] : 0;
     const int q = (int)(end - beg);
     int st = q <= 0 ? 1 : 0;
-    if (st == 0) {
+    {
       bool bad_idx = false, bad_val = false;
-      for (int64_t t = beg + lane; t < end; t += kWave) {
+      for (int64_t t = beg + jc + 16 * g; st == 0 && t < end; t += 32) {
         const int j = col[t];
         bad_idx = bad_idx || j < 0 || j >= n;
         bad_val = bad_val || !__builtin_isfinite(val[t]);
       }
-      if (__ballot(bad_idx)) st = 5;
-      else if (__ballot(bad_val)) st = 3;
+      if (st == 0 && (__ballot(bad_idx) & appmask)) st = 5;
+      else if (st == 0 && (__ballot(bad_val) & appmask)) st = 3;
     }
-    float e[16];  // e[v] = embedding K(v, g)
+    const bool live = has && st == 0;
+    float e[16];  // e[v] = embedding K(v, g) of this lane's application
 #pragma unroll
     for (int v = 0; v < 16; ++v) e[v] = 0.f;
     float lossv = 0.f;
-    if (st == 0) {
-      const float inv_q = 1.f / (float)q;
+    const int qt = live ? (q + 15) >> 4 : 0;
+    const int ntiles = max(qt, __shfl_xor(qt, 16, kWave));  // the same in every lane
+    if (ntiles > 0) {
+      const float inv_q = live ? 1.f / (float)q : 0.f;
       for (int it = 0; it <= steps; ++it) {
         // a at this lane's hidden units
         asm volatile("" : "+v"(toff));
@@ -143,12 +154,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           for (int s2 = 0; s2 < 16; ++s2) a[b] = mfma32(T(kNcfTA, 16 * b + s2), e[s2], a[b]);
         f16 de = {};
         float sq = 0.f;
-        for (int64_t t0 = beg; t0 < end; t0 += 32) {
+        for (int tt = 0; tt < ntiles; ++tt) {
           asm volatile("" : "+v"(toff));
-          const bool valid = t0 + jl < end;
-          const int64_t t = valid ? t0 + jl : beg;
-          const float* crow = C + (int64_t)col[t] * kNcfH;
-          const float r = val[t];
+          const int64_t t = beg + 16 * tt + jc;
+          const bool valid = live && t < end;
+          const float *crow = C + (int64_t)(valid ? col[t] : 0) * kNcfH;
+          const float r = valid ? val[t] : 0.f;
           // forward: Z2 = b2 + W2 SELU(a + c)
           f16 z2[2];
 #pragma unroll
@@ -165,7 +176,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int ob = 0; ob < 2; ++ob) z2[ob] = mfma32(T(kNcfTF, 32 * ob + q2), h1, z2[ob]);
           }
-          // output and residual of observation jl (both halves hold half of the sum)
+          // output and residual of this column's observation (each half holds half of the sum)
           float yp = 0.f;
 #pragma unroll
           for (int b = 0; b < 2; ++b)
@@ -198,29 +209,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           float ee = 0.f;
 #pragma unroll
           for (int v = 0; v < 16; ++v) ee = __builtin_fmaf(e[v], e[v], ee);
-          // sq: one value per observation in each half; ee: each half holds its 16 indices
-          const float sqt = wave_sum_f(g == 0 ? sq : 0.f);
-          const float eet = __shfl(ee, 0, kWave) + __shfl(ee, 32, kWave);
-          lossv = sqt * inv_q + mu * eet;
+          // squared residuals: one per column in each half; embedding: each half holds 16 indices
+          float sqt = g == 0 ? sq : 0.f;
+#pragma unroll
+          for (int off = 1; off < 16; off <<= 1) sqt += __shfl_xor(sqt, off, kWave);
+          lossv = sqt * inv_q + mu * (ee + __shfl_xor(ee, 32, kWave));
           break;
         }
-        // sum DE over the observation columns (the 32 lanes of each half), then the step
+        // sum DE over the application's 16 columns, then the step
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           float x = de[v];
 #pragma unroll
-          for (int off = 1; off < 32; off <<= 1) x += __shfl_xor(x, off, kWave);
-          e[v] -= eta * (x + 2.f * mu * e[v]);
+          for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off, kWave);
+          if (live) e[v] -= eta * (x + 2.f * mu * e[v]);
         }
       }
     }
-    if (jl == 0) {
+    if (has && jc == 0) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) E[i * kNcfD + ncf_row(v, g)] = e[v];
-    }
-    if (lane == 0) {
-      if (Lout) Lout[i] = st == 0 ? lossv : 0.f;
-      if (status) status[i] = st;
+      if (g == 0) {
+        if (Lout) Lout[i] = live ? lossv : 0.f;
+        if (status) status[i] = st;
+      }
     }
   }
 }
@@ -249,7 +261,8 @@ extern "C" open_status open_ncf_foldin(open_ctx *ctx, const float *S, int32_t n,
   OPEN_LAUNCH(ctx, "ncf_table", k_ncf_table, dim3((unsigned)((tt + 255) / 256)), dim3(256), 0, S, n, W1, b1,
               (float *)tab);
   const int64_t cap = (int64_t)ctx->num_cu * 16;  // waves
-  const int64_t waves = m < cap ? m : cap;
+  const int64_t pairs = (m + 1) / 2;  // two applications per wavefront
+  const int64_t waves = pairs < cap ? pairs : cap;
   OPEN_LAUNCH(ctx, "ncf_foldin", k_ncf_foldin, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, m, row_ptr, col, val,
               n, (const float *)tab, W1, W2, b2, w3, b3, steps, eta, mu, E_out, loss_out, row_status);
   return OPEN_OK;

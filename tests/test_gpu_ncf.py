@@ -70,7 +70,7 @@ def test_parity_mixed_counts(ctx):
     # the fold-in count range plus very short and longer rows
     grid = synth.grid_of("foldin")
     S, p = model(grid.n)
-    rows = synth.draw_rows(3, grid, 700, ("uniform", 1, 70), seed=21)
+    rows = synth.draw_rows(3, grid, 701, ("uniform", 1, 70), seed=21)  # odd: the last pair is one app
     E, L, st = run(ctx, S, p, rows.row_ptr, rows.col, rows.val)
     compare("ncf mixed", E, L, st, ncf.foldin(rows.row_ptr, rows.col, rows.val, S, p, C["steps"], C["eta"], C["mu"]),
             S, p, rows.row_ptr, rows.col, rows.val)
@@ -79,18 +79,20 @@ def test_parity_mixed_counts(ctx):
 def test_step_counts_and_statuses(ctx):
     grid = synth.grid_of("foldin")
     S, p = model(grid.n, seed=1)
-    rows = synth.draw_rows(3, grid, 64, ("uniform", 4, 24), seed=22)
+    rows = synth.draw_rows(3, grid, 63, ("uniform", 4, 24), seed=22)
     for steps in (0, 1, 7):
         E, L, st = run(ctx, S, p, rows.row_ptr, rows.col, rows.val, steps=steps)
         compare("ncf steps=%d" % steps, E, L, st,
                 ncf.foldin(rows.row_ptr, rows.col, rows.val, S, p, steps, C["eta"], C["mu"]), S, p, rows.row_ptr,
                 rows.col, rows.val)
-    rp = np.array([0, 0, 2, 4, 6], dtype=np.int64)
-    col = np.array([1, 2, 3, grid.n, 5, 6], dtype=np.int32)
-    val = np.array([0.5, 0.6, 0.7, 0.8, np.nan, 0.9], dtype=np.float32)
+    # status rows next to good rows of the same wavefront pair (empty | good, bad index | NaN,
+    # good | empty)
+    rp = np.array([0, 0, 2, 4, 6, 9, 9], dtype=np.int64)
+    col = np.array([1, 2, 3, grid.n, 5, 6, 7, 8, 9], dtype=np.int32)
+    val = np.array([0.5, 0.6, 0.7, 0.8, np.nan, 0.9, 0.4, 0.5, 0.6], dtype=np.float32)
     E, L, st = run(ctx, S, p, rp, col, val, steps=10)
-    assert st.tolist() == [1, 0, 5, 3]
-    assert (E[[0, 2, 3]] == 0).all() and (L[[0, 2, 3]] == 0).all()
+    assert st.tolist() == [1, 0, 5, 3, 0, 1]
+    assert (E[[0, 2, 3, 5]] == 0).all() and (L[[0, 2, 3, 5]] == 0).all()
     compare("ncf status rows", E, L, st, ncf.foldin(rp, col, val, S, p, 10, C["eta"], C["mu"]), S, p, rp, col, val)
 
 
