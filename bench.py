@@ -57,8 +57,9 @@ def kernel_of_counts(n, k):
 
 
 def recorded_traffic(kernel, choice):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
-    the summary covers another kernel or variant, or the kernel's sources changed since."""
+    """HBM bytes per launch of `kernel` in its chosen variant from the committed rocprofv3
+    counter summary, or None when the summary covers another kernel or variant, or the kernel's
+    sources changed since."""
     import hashlib
     path = os.path.join(HERE, "profiles", "ridge_foldin_1M_k32.md")
     if not os.path.exists(path):
@@ -67,7 +68,10 @@ def recorded_traffic(kernel, choice):
     for line in open(path):
         if line.startswith("traffic-record: "):
             rec = json.loads(line[len("traffic-record: "):])
-    if not rec or rec.get("kernel") != kernel or rec.get("choice") != choice:
+    if not rec or rec.get("kernel") != kernel:
+        return None
+    by_choice = rec.get("traffic_by_choice", {})
+    if str(choice) not in by_choice and rec.get("choice") != choice:
         return None
     h = hashlib.sha1()
     for f in rec["sources"]:
@@ -75,7 +79,7 @@ def recorded_traffic(kernel, choice):
             h.update(fh.read())
     if h.hexdigest()[:16] != rec["sources_sha1"]:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return by_choice.get(str(choice), rec["traffic_bytes_per_launch"])
 
 
 def surrogate_leg(args, ctx, dV, drp, dcol, dval, m, steps, warmup, log):
