@@ -64,7 +64,7 @@ __device__ __forceinline__ f16 mfma32(float a, float b, f16 c) {
 }
 __device__ __forceinline__ int ncf_row(int v, int g) { return 8 * (v >> 2) + 4 * g + (v & 3); }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ncf_foldin(int64_t m, const int64_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ncf_foldin(int64_t m, const RowRef *__restrict__ list,
                                                     const int32_t *__restrict__ col, const float *__restrict__ val,
                                                     int n, const float *__restrict__ C, const float *__restrict__ W1,
                                                     const float *__restrict__ W2, const float *__restrict__ b2,
@@ -120,10 +120,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int64_t npairs = (m + 1) >> 1;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t pr = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); pr < npairs; pr += nw) {
-    const int64_t i = 2 * pr + half;  // this lane's application
-    const bool has = i < m;
-    const int64_t beg = has ? ptr[i] : 0, end = has ? ptr[i + 1] : 0;
-    const int q = (int)(end - beg);
+    const int64_t li = 2 * pr + half;  // this lane's application: entry li of the size-ordered list
+    const bool has = li < m;
+    const RowRef rec = has ? list[li] : RowRef{0, 0, 0};
+    const int64_t i = rec.row, beg = rec.beg, end = rec.beg + rec.cnt;
+    const int q = rec.cnt;
     int st = q <= 0 ? 1 : 0;
     {
       bool bad_idx = false, bad_val = false;
@@ -251,6 +252,7 @@ extern "C" open_status open_ncf_foldin(open_ctx *ctx, const float *S, int32_t n,
   if (n < 1 || m < 0 || steps < 0 || steps > kNcfMaxSteps || !(eta == eta) || !(mu == mu))
     return fail(ctx, OPEN_E_INVALID, "bad sizes, steps, eta or mu");
   if (m == 0) return OPEN_OK;
+  if (m > INT32_MAX) return fail(ctx, OPEN_E_UNSUPPORTED, "more than 2^31 - 1 rows");
   if (!S || !W1 || !b1 || !W2 || !b2 || !w3 || !b3 || !row_ptr || !col || !val || !E_out)
     return fail(ctx, OPEN_E_INVALID, "null pointer");
   OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -260,10 +262,16 @@ extern "C" open_status open_ncf_foldin(open_ctx *ctx, const float *S, int32_t n,
   const int64_t tt = (int64_t)n * kNcfH;
   OPEN_LAUNCH(ctx, "ncf_table", k_ncf_table, dim3((unsigned)((tt + 255) / 256)), dim3(256), 0, S, n, W1, b1,
               (float *)tab);
+  // applications in order of observed count, so that the two of a wavefront need about as
+  // many observation tiles
+  RowRef *list = nullptr;
+  int64_t *cls = nullptr;
+  if ((st = bucket_rows(ctx, m, row_ptr, kNcfD, &list, &cls, kSplitMin))) return st;
   const int64_t cap = (int64_t)ctx->num_cu * 16;  // waves
   const int64_t pairs = (m + 1) / 2;  // two applications per wavefront
   const int64_t waves = pairs < cap ? pairs : cap;
-  OPEN_LAUNCH(ctx, "ncf_foldin", k_ncf_foldin, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, m, row_ptr, col, val,
-              n, (const float *)tab, W1, W2, b2, w3, b3, steps, eta, mu, E_out, loss_out, row_status);
+  OPEN_LAUNCH(ctx, "ncf_foldin", k_ncf_foldin, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, m,
+              (const RowRef *)list, col, val, n, (const float *)tab, W1, W2, b2, w3, b3, steps, eta, mu, E_out,
+              loss_out, row_status);
   return OPEN_OK;
 }
