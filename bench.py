@@ -275,8 +275,8 @@ def predictor_leg(ctx, rows, grid, steps, warmup, log):
 
 
 def ncf_leg(ctx, steps, warmup, log):
-    """NCF fold-in (SELU network, embedding learned by 30 gradient steps per new app) for
-    65,536 new apps with 4-24 observed settings each: apps per second.  Algorithmic work per
+    """NCF fold-in (SELU network, embedding learned by 30 gradient steps per new app, products
+    on FP32 MFMA) for 65,536 new apps with 4-24 observed settings each: apps per second.  Algorithmic work per
     observed entry and step: forward 2 (32*64 + 64*64 + 64) flop, backward 2 (64 + 64*64)
     flop, plus 2*32*64 flop per app and step for the embedding layer both ways."""
     import numpy as np
@@ -311,7 +311,7 @@ def ncf_leg(ctx, steps, warmup, log):
     return {"workload": "NCF fold-in: %d new apps x 480 settings, 4-24 observed, embedding 32, SELU 64-64, "
                         "%d gradient steps" % (m, c["steps"]),
             "apps_per_s": m / (ms * 1e-3), "ms_per_call": ms, "mean_final_loss": float(L.mean().item()),
-            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops}}
 
 
