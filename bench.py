@@ -444,8 +444,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; the data-parallel path shards rows across GPUs "
-              "with no exchange (see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: only one GPU is measured; the row-parallel legs would shard rows across GPUs "
+              "with no exchange. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
