@@ -60,23 +60,52 @@ def loss(e, S, r, p, mu):
     return float(np.mean((y - r) ** 2) + mu * (e @ e))
 
 
-def grad(e, S, r, p, mu):
-    """dL/de by the chain rule, layer by layer backwards."""
+def grad(e, S, r, p, mu, flip=None):
+    """dL/de by the chain rule, layer by layer backwards.  flip = (layer, obs, unit), when
+    given, evaluates SELU's derivative at that one pre-activation on the other side of the
+    kink (the right-hand value lam where the left-hand one applies, and the reverse); the
+    tests use it to describe a trajectory whose pre-activation sits at 0 within rounding."""
     q, d = S.shape
     y, Z1, Z2 = forward(e, S, p)
     dy = 2.0 * (y - r) / q
-    dZ2 = dy[:, None] * p["w3"][None, :] * selu_grad(Z2)
+    G1, G2 = selu_grad(Z1), selu_grad(Z2)
+    if flip is not None:
+        layer, o, u = flip
+        Z, G = (Z1, G1) if layer == 1 else (Z2, G2)
+        z = Z[o, u]
+        G[o, u] = SELU_LAMBDA * SELU_ALPHA * math.exp(min(z, 0.0)) if z > 0 else SELU_LAMBDA
+    dZ2 = dy[:, None] * p["w3"][None, :] * G2
     dH1 = dZ2 @ p["W2"]
-    dZ1 = dH1 * selu_grad(Z1)
+    dZ1 = dH1 * G1
     dX = dZ1 @ p["W1"]
     return dX[:, :d].sum(axis=0) + 2.0 * mu * e
 
 
-def foldin_row(S_obs, r, p, steps, eta, mu):
+def foldin_row(S_obs, r, p, steps, eta, mu, flip=None):
+    """T steps of gradient descent from e = 0.  flip = (step, layer, obs, unit) takes SELU's
+    derivative on the other side of the kink at that one evaluation (see grad)."""
     e = np.zeros(S_obs.shape[1])
-    for _ in range(steps):
-        e = e - eta * grad(e, S_obs, r, p, mu)
+    for t in range(steps):
+        f = flip[1:] if flip is not None and flip[0] == t else None
+        e = e - eta * grad(e, S_obs, r, p, mu, f)
     return e
+
+
+def kink_events(S_obs, r, p, steps, eta, mu, eps):
+    """Pre-activations within eps of SELU's kink along the trajectory of foldin_row: a list
+    of (|z|, step, layer, obs, unit), nearest first.  Where |z| is below the rounding error
+    of a lower-precision evaluation, that evaluation may take SELU's derivative from the other
+    side; each event is one such decision."""
+    p = _f64(p)
+    e = np.zeros(S_obs.shape[1])
+    out = []
+    for t in range(steps):
+        _, Z1, Z2 = forward(e, S_obs, p)
+        for layer, Z in ((1, Z1), (2, Z2)):
+            for o, u in zip(*np.nonzero(np.abs(Z) < eps)):
+                out.append((abs(float(Z[o, u])), t, layer, int(o), int(u)))
+        e = e - eta * grad(e, S_obs, r, p, mu)
+    return sorted(out)
 
 
 def foldin(row_ptr, col, val, S, p, steps, eta, mu, rows=None):

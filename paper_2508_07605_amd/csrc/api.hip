@@ -33,6 +33,7 @@ open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out) {
       return fail(ctx, OPEN_E_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
     }
     ctx->ws_bytes[slot] = want;
+    ++ctx->ws_gen;
   }
   *out = ctx->ws[slot];
   return OPEN_OK;
@@ -238,16 +239,6 @@ static open_status foldin_prepare(open_ctx *ctx, const float *F, int32_t n, int3
     *nnz_split = *h;
   }
   if ((st = bucket_rows(ctx, m, row_ptr, k, list, cls, *nnz_split >= 0 ? kSplitMin : INT64_MAX))) return st;
-  if (k == 64) {
-    // rank 64 solves the dual form (n_i <= 32) and the split-K form (n_i >= kSplitMin)
-    int64_t *h;
-    if ((st = pinned_get(ctx, sizeof(int64_t) * 2 * kNumClasses, (void **)&h))) return st;
-    OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, *cls, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToHost, ctx->stream));
-    OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    int64_t big = 0;
-    for (int c = 9; c < kSplitClass; ++c) big += h[2 * c + 1];
-    if (big) return fail(ctx, OPEN_E_UNSUPPORTED, "rank 64 with 33 to 1023 observed entries in a row");
-  }
   return OPEN_OK;
 }
 
@@ -285,6 +276,7 @@ open_status open_foldin_graph(open_ctx *ctx, const float *F, int32_t n, int32_t 
   key.U = U_out;
   key.status = row_status;
   if (rank_ok(k)) memcpy(key.tune, ctx->tune[rank_index(k)], sizeof(key.tune));
+  key.ws_gen = ctx->ws_gen;
   if (ctx->graph_exec && memcmp(&key, &ctx->gkey, sizeof(key)) == 0) {
     OPEN_HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
     return OPEN_OK;
@@ -308,6 +300,7 @@ open_status open_foldin_graph(open_ctx *ctx, const float *F, int32_t n, int32_t 
   }
   ctx->graph = g;
   ctx->graph_exec = ex;
+  key.ws_gen = ctx->ws_gen;  // the eager pass may have grown a workspace before the recording
   memcpy(&ctx->gkey, &key, sizeof(key));  // byte copy: the key is compared with memcmp
   return OPEN_OK;
 }

@@ -5,6 +5,7 @@
 //   class 0              empty rows
 //   classes 1..8         dual form, system dimension padded to 4*class (n_i <= min(k, 32))
 //   classes 9..15        primal form (k x k system), n_i in (k 2^p, k 2^(p+1)], p = class - 9
+//                        (class 9 also takes n_i in (32, 64] at rank 64)
 //   class 16             rows long enough for the split-K path
 // Exact integer work; the resulting list is independent of scheduling.
 #include "common.h"
@@ -27,8 +28,10 @@ __device__ __forceinline__ int row_class(int64_t cnt, int k, int64_t split_min) 
   const int dmax = k < 32 ? k : 32;
   if (cnt <= dmax) return (int)((cnt + 3) >> 2);
   if (cnt >= split_min) return kSplitClass;
-  const int64_t r = (cnt - 1) / k;  // >= 1 here
-  int p = 63 - __clzll((unsigned long long)r);
+  // primal: class 9 + floor(log2((n_i - 1) / k)), at least 9 (rank 64 reaches here from
+  // n_i = 33, where (n_i - 1) / k is still 0)
+  const int64_t r = (cnt - 1) / k;
+  int p = r > 0 ? 63 - __clzll((unsigned long long)r) : 0;
   p = p > 6 ? 6 : p;
   return 9 + p;
 }

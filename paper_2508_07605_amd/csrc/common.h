@@ -116,6 +116,8 @@ struct open_ctx {
   };
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};
+  // bumped whenever a workspace is reallocated: a recorded graph holds the old addresses
+  uint64_t ws_gen = 0;
   // chosen kernel variant of each size-class group, per rank (8, 16, 32, 64); 0 = default
   int8_t tune[4][16] = {};
   // graph capture: while capturing, launches go to cap_stream and nothing may allocate or sync
@@ -134,6 +136,7 @@ struct open_ctx {
     float *U;
     int32_t *status;
     int8_t tune[16];
+    uint64_t ws_gen;  // the workspace addresses the recording refers to
   } gkey = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;

@@ -435,23 +435,6 @@ open_status open_fit(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const int64
       st = fail(ctx, OPEN_E_DEVICE, "copy");
       break;
     }
-    if (k == 64) {
-      int64_t h[4 * kNumClasses];
-      if (hipMemcpyAsync(h, cls_r, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToHost, ctx->stream) ||
-          hipMemcpyAsync(h + 2 * kNumClasses, cls_c, sizeof(int64_t) * 2 * kNumClasses, hipMemcpyDeviceToHost,
-                         ctx->stream) ||
-          hipStreamSynchronize(ctx->stream)) {
-        st = fail(ctx, OPEN_E_DEVICE, "copy");
-        break;
-      }
-      int64_t big = 0;
-      for (int cc = 9; cc < kSplitClass; ++cc) big += h[2 * cc + 1] + h[2 * kNumClasses + 2 * cc + 1];
-      if (big) {
-        st = fail(ctx, OPEN_E_UNSUPPORTED,
-                  "rank 64 with 33 to 1023 observed entries in a row or column (dual form up to 32, split-K from 1024)");
-        break;
-      }
-    }
     auto sweep = [&]() -> open_status {
       open_status e;
       if ((e = rowsolve_launch(ctx, V, n, k, row_ptr, col, val, lambda, weighted, list_r, cls_r, U, nullptr, m)))

@@ -634,5 +634,6 @@ OPEN_GROUP(g_k64_d20);
 OPEN_GROUP(g_k64_d24);
 OPEN_GROUP(g_k64_d28);
 OPEN_GROUP(g_k64_d32);
+OPEN_GROUP(g_k64_primal);
 
 }  // namespace openk

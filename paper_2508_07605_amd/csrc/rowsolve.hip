@@ -41,6 +41,7 @@ const ClassGroup *class_groups(int k, int *count) {
       {"ridge_k64_d24", 6, 6, 2, g_k64_d24},
       {"ridge_k64_d28", 7, 7, 2, g_k64_d28},
       {"ridge_k64_d32", 8, 8, 2, g_k64_d32},
+      {"ridge_k64_primal", 9, 15, 1, g_k64_primal},
   };
   switch (k) {
     case 8: *count = (int)(sizeof(g8) / sizeof(g8[0])); return g8;

@@ -110,9 +110,8 @@ def draw_counts(r: np.random.Generator, m: int, n: int, spec) -> np.ndarray:
     raise ValueError(spec)
 
 
-def draw_sets(r: np.random.Generator, counts: np.ndarray, n: int):
-    """Uniform subsets without replacement, sorted within each row.
-    Returns CSR (row_ptr int64[m+1], col int32[nnz])."""
+def _sets_by_keys(r: np.random.Generator, counts: np.ndarray, n: int):
+    """Uniform c-subsets of [0, n) by random keys: the c smallest of n iid keys per row."""
     m = len(counts)
     row_ptr = np.zeros(m + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
@@ -135,6 +134,68 @@ def draw_sets(r: np.random.Generator, counts: np.ndarray, n: int):
         keep = np.arange(cmax)[None, :] < c[:, None]
         part = np.sort(np.where(keep, part, n), axis=1)
         col[row_ptr[s]:row_ptr[e]] = part[keep].astype(np.int32)
+    return row_ptr, col
+
+
+def _sets_by_draws(r: np.random.Generator, counts: np.ndarray, n: int):
+    """Uniform c-subsets of [0, n) for rows with c much smaller than n: iid uniform draws
+    (2c + 16 per row), keeping the first c distinct values in draw order, which is sampling
+    without replacement.  Returns (sorted columns per row as CSR pieces, rows that drew fewer
+    than c distinct values)."""
+    m = len(counts)
+    over = 2 * counts + 16
+    optr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(over, out=optr[1:])
+    rid = np.repeat(np.arange(m, dtype=np.int64), over)
+    key = rid * n + r.integers(0, n, size=int(optr[-1]))
+    order = np.argsort(key, kind="stable")  # equal keys stay in draw order
+    ks = key[order]
+    new = np.ones(len(ks), dtype=bool)
+    new[1:] = ks[1:] != ks[:-1]
+    first = np.zeros(len(key), dtype=bool)
+    first[order[new]] = True
+    rank = np.cumsum(first) - 1
+    rank -= np.repeat(np.concatenate([[0], np.cumsum(first)[optr[1:-1] - 1]]) if m > 1 else np.zeros(1, np.int64),
+                      over)
+    keep = first & (rank < np.repeat(counts, over))
+    got = np.bincount(rid[keep], minlength=m)
+    ks_keep = ks[keep[order]]  # kept keys, already sorted (row-major, then column)
+    return ks_keep, got
+
+
+def draw_sets(r: np.random.Generator, counts: np.ndarray, n: int):
+    """Uniform subsets without replacement, sorted within each row.
+    Returns CSR (row_ptr int64[m+1], col int32[nnz]).  Grids of 1024 or more settings draw
+    the sparse rows (c <= n / 4) by iid draws with rejection of repeats, the rest by keys."""
+    if n < 1024:
+        return _sets_by_keys(r, counts, n)
+    m = len(counts)
+    counts = np.asarray(counts, dtype=np.int64)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = np.empty(int(row_ptr[-1]), dtype=np.int32)
+    sparse = counts <= n // 4
+    chunk = 200_000
+    redo = [np.nonzero(~sparse)[0]]
+    sp_idx = np.nonzero(sparse)[0]
+    for s in range(0, len(sp_idx), chunk):
+        ids = sp_idx[s:s + chunk]
+        ks, got = _sets_by_draws(r, counts[ids], n)
+        ok = got == counts[ids]
+        rows_of = ks // n
+        good = ok[rows_of]
+        kcol = (ks[good] % n).astype(np.int32)
+        # scatter the complete rows to their CSR ranges (rows stay in order within the chunk)
+        okids = ids[ok]
+        dst = np.repeat(row_ptr[okids], counts[okids]) + (
+            np.arange(int(counts[okids].sum())) - np.repeat(np.cumsum(counts[okids]) - counts[okids], counts[okids]))
+        col[dst] = kcol
+        redo.append(ids[~ok])
+    redo = np.sort(np.concatenate(redo))
+    if len(redo):
+        rp, c2 = _sets_by_keys(r, counts[redo], n)
+        dst = np.repeat(row_ptr[redo], counts[redo]) + (np.arange(int(rp[-1])) - np.repeat(rp[:-1], counts[redo]))
+        col[dst] = c2
     return row_ptr, col
 
 

@@ -68,7 +68,7 @@ def test_objective_and_residual(ctx, k):
     assert np.abs(rho - ref).max() <= 1e-5 * ref.max()
 
 
-@pytest.mark.parametrize("name", ["fit", "fit_d5"])
+@pytest.mark.parametrize("name", ["fit", "fit_d5", "large"])
 def test_half_sweeps_from_generator_inputs(ctx, name):
     # one row half-sweep (against V0) and one column half-sweep (against U0), both from the
     # generator's initial factors, compared row by row and column by column
@@ -164,3 +164,37 @@ def test_refit_warm_start(ctx, sweeps):
         assert np.abs(obj - objr).max() / objr.max() <= 1e-4
     else:
         assert np.array_equal(host(U)[:m_old], U0[:m_old])
+
+
+@pytest.mark.timeout(600)
+def test_large_config_fit_sampled(ctx):
+    # the large configuration at full size: 2M apps x 1920 settings, ~2 % density, rank 64.
+    # One ALS-WR sweep from the generator's initial factors; the oracle recomputes a seeded
+    # sample of 10,000 rows from V0 (the input of the row half-sweep) and 64 columns from the
+    # GPU's U (the input of the column half-sweep).
+    import time
+    t0 = time.time()
+    c, grid, rows = fit_rows("large")
+    U0, V0 = synth.init_factors(c["cfg_id"], rows.m, grid.n, c["k"])
+    print("large: %d rows, %d entries generated in %.1f s" % (rows.m, rows.nnz, time.time() - t0), flush=True)
+    U, V = dev(U0), dev(V0)
+    native.open_fit(ctx, dev(rows.row_ptr), dev(rows.col), dev(rows.val), U, V, c["lam"], 1, True, want_obj=False)
+    Ug, Vg = host(U), host(V)
+    assert np.isfinite(Ug).all() and np.isfinite(Vg).all()
+    r = np.random.default_rng(2025)
+    srows = np.sort(r.choice(rows.m, size=10_000, replace=False))
+    ref, st = oracle.ridge_subset(srows, rows.row_ptr, rows.col, rows.val, V0, c["lam"], True)
+    assert (st == 0).all()
+    e = np.linalg.norm(Ug[srows] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    cnt = np.diff(rows.row_ptr)[srows]
+    print("large row half-sweep (10,000 rows; %d with more than 32 entries): max %.3e p99 %.3e median %.3e"
+          % ((cnt > 32).sum(), e.max(), np.percentile(e, 99), np.median(e)), flush=True)
+    assert e.max() <= 1e-4
+    rcp, rri, rcv = oracle.csr_to_csc(rows.row_ptr, rows.col, rows.val, grid.n)
+    scols = np.sort(r.choice(grid.n, size=64, replace=False))
+    refc, stc = oracle.ridge_subset(scols, rcp, rri, rcv, Ug, c["lam"], True)
+    assert (stc == 0).all()
+    ec = np.linalg.norm(Vg[scols] - refc, axis=1) / np.linalg.norm(refc, axis=1)
+    print("large column half-sweep (64 columns, %d-%d entries): max %.3e median %.3e"
+          % (np.diff(rcp)[scols].min(), np.diff(rcp)[scols].max(), ec.max(), np.median(ec)), flush=True)
+    assert ec.max() <= 1e-4

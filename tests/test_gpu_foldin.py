@@ -62,11 +62,12 @@ def test_foldin_config_shape(ctx):
     assert e.max() <= TOL
 
 
-@pytest.mark.parametrize("k,n,maxc", [(8, 120, 120), (16, 120, 120), (32, 480, 480), (64, 480, 32)])
+@pytest.mark.parametrize("k,n,maxc", [(8, 120, 120), (16, 120, 120), (32, 480, 480), (64, 480, 480),
+                                       (64, 1300, 1300)])
 @pytest.mark.parametrize("weighted", [True, False])
 def test_every_size_class(ctx, k, n, maxc, weighted):
-    # every count from 0 to maxc at least a few times: empty rows, all dual classes and,
-    # for k <= 32, the primal classes
+    # every count from 0 to maxc at least a few times: empty rows, all dual classes, the
+    # primal classes and, with 1024 or more factor rows, the split-K rows
     r = np.random.default_rng(100 + k)
     counts = np.concatenate([np.repeat(np.arange(0, maxc + 1), 3), r.integers(0, maxc + 1, size=517)])
     r.shuffle(counts)
@@ -286,6 +287,33 @@ def test_foldin_graph_replays(ctx):
     # the result also matches the oracle
     ref64, _ = oracle.ridge_rows(a.row_ptr, a.col, dval.cpu().numpy(), dV.cpu().numpy(), 0.1, True)
     assert rel_err(U.cpu().numpy().astype(np.float64), ref64).max() <= TOL
+
+
+def test_foldin_graph_after_workspace_growth(ctx):
+    # a larger call between two replays reallocates the bucketing workspaces the recording
+    # points at: the next call with the recorded arguments must record again, not replay
+    grid = synth.grid_of("foldin")
+    V = synth.setting_factors(3, grid, 32, m_ref=1024)
+    a = synth.draw_rows(3, grid, 5003, ("uniform", 4, 24), seed=41)
+    big = synth.draw_rows(3, grid, 300_007, ("uniform", 4, 24), seed=42)
+    dV, drp, dcol, dval = dev(V), dev(a.row_ptr), dev(a.col), dev(a.val)
+    U = torch.empty((a.m, 32), dtype=torch.float32, device="cuda")
+    native.open_foldin_graph(ctx, dV, drp, dcol, dval, 0.05, True, U_out=U)
+    native.open_foldin_graph(ctx, dV, drp, dcol, dval, 0.05, True, U_out=U)  # replay
+    Ubig = native.open_foldin(ctx, dV, dev(big.row_ptr), dev(big.col), dev(big.val), 0.05, True)
+    dval.copy_(dev(np.ascontiguousarray(a.val[::-1])))
+    U.zero_()
+    native.open_foldin_graph(ctx, dV, drp, dcol, dval, 0.05, True, U_out=U)
+    native.open_foldin_graph(ctx, dV, drp, dcol, dval, 0.05, True, U_out=U)  # replay of the new recording
+    torch.cuda.synchronize()
+    ref = native.open_foldin(ctx, dV, drp, dcol, dval, 0.05, True)
+    torch.cuda.synchronize()
+    assert torch.equal(U, ref)
+    ref64, _ = oracle.ridge_rows(a.row_ptr, a.col, a.val[::-1], V, 0.05, True)
+    assert rel_err(U.cpu().numpy().astype(np.float64), ref64).max() <= TOL
+    sample = np.arange(0, big.m, 97)
+    refb, _ = oracle.ridge_subset(sample, big.row_ptr, big.col, big.val, V, 0.05, True)
+    assert rel_err(Ubig.cpu().numpy()[sample].astype(np.float64), refb).max() <= TOL
 
 
 def test_foldin_graph_unsupported_shapes(ctx):

@@ -1,16 +1,19 @@
 """GPU parity of the NCF fold-in (Section III-B.1 model, gradient-descent embedding of new
 applications) against the FP64 oracle, through the C ABI.
 
-SELU's derivative jumps at 0 (lambda on the right, lambda * alpha on the left), so a
-pre-activation that lands within rounding distance of 0 somewhere along a row's 30 steps can
-take the other branch in float32 than in float64; the two trajectories then part by a small
-finite amount and both are valid gradient-descent runs.  The checks are therefore:
+SELU's derivative jumps at 0 (lambda on the right, lambda * alpha on the left).  Where a
+pre-activation along a row's trajectory lies within float32 rounding of 0, the kernel can take
+the derivative from the other side than the FP64 oracle does; that one decision moves the
+trajectory by a finite amount, and both are valid gradient-descent runs.  The checks are:
   * statuses equal;
-  * per row e = |E - E_ref| / |E_ref|: 99 % of rows within 1e-4 (float32 forward and backward
-    passes over 30 contracting steps), every row within 5e-2;
-  * what does not depend on the branch taken: the loss the oracle evaluates at the GPU's
-    embedding is within 1e-3 (relative) of the oracle's own final loss, and the loss the GPU
-    reports equals the oracle's evaluation at the GPU's embedding within 1e-4."""
+  * every row within 1e-4 (e = |E - E_ref| / |E_ref|) of the oracle's trajectory, except rows
+    whose FP64 trajectory has a pre-activation within EPS_KINK of 0 (the float32 rounding of a
+    pre-activation is far below that); such a row must be within 1e-4 of the oracle
+    trajectory that takes the other side at one of those pre-activations.  The test prints how
+    many rows were excused this way and which event explains each;
+  * the loss the oracle evaluates at the GPU's embedding is within 1e-3 (relative) of the
+    oracle's own final loss, and the loss the GPU reports equals the oracle's evaluation at the
+    GPU's embedding within 1e-4."""
 import numpy as np
 import pytest
 import torch
@@ -50,18 +53,54 @@ def run(ctx, S, p, rp, col, val, steps=C["steps"], eta=C["eta"], mu=C["mu"]):
     return E.cpu().numpy().astype(np.float64), L.cpu().numpy().astype(np.float64), st.cpu().numpy()
 
 
-def compare(name, E, L, st, ref, S, p, rp, col, val, rows=None):
-    Er, Lr, str_ = ref
-    assert np.array_equal(st, str_)
+EPS_KINK = 1e-6
+
+
+def kink_explained(E, Er, S, p, rp, col, val, rows, steps, eta, mu):
+    """Per-row error against the oracle and, for rows beyond TOL, against the oracle
+    trajectories that take SELU's derivative from the other side at one pre-activation within
+    EPS_KINK of 0.  Returns (e_nominal, e_explained, notes)."""
+    S64 = np.asarray(S, np.float64)
+    p64 = {k: np.asarray(v, np.float64) for k, v in p.items()}
     nrm = np.maximum(np.linalg.norm(Er, axis=1), 1e-3)
     e = np.linalg.norm(E - Er, axis=1) / nrm
-    Lg = ncf.loss_rows(rp, col, val, S, p, C["mu"], E, rows=rows)  # oracle loss at the GPU embedding
+    best = e.copy()
+    notes = []
+    for t in np.nonzero(e > TOL)[0]:
+        i = rows[t]
+        a, b = int(rp[i]), int(rp[i + 1])
+        c = np.asarray(col[a:b], np.int64)
+        r = np.asarray(val[a:b], np.float64)
+        events = ncf.kink_events(S64[c], r, p64, steps, eta, mu, EPS_KINK)
+        for ev in events:
+            alt = ncf.foldin_row(S64[c], r, p64, steps, eta, mu, flip=ev[1:])
+            err = np.linalg.norm(E[t] - alt) / nrm[t]
+            if err < best[t]:
+                best[t] = err
+                note = (int(i), float(e[t]), float(err), ev)
+        if best[t] < e[t]:
+            notes.append(note)
+    return e, best, notes
+
+
+def compare(name, E, L, st, ref, S, p, rp, col, val, rows=None, steps=C["steps"], eta=C["eta"], mu=C["mu"]):
+    Er, Lr, str_ = ref
+    assert np.array_equal(st, str_)
+    rows = np.arange(len(rp) - 1) if rows is None else np.asarray(rows)
+    e, best, notes = kink_explained(E, Er, S, p, rp, col, val, rows, steps, eta, mu)
+    Lg = ncf.loss_rows(rp, col, val, S, p, mu, E, rows=rows)  # oracle loss at the GPU embedding
     den = np.maximum(np.abs(Lr), 1e-3)
     reach = (Lg - Lr) / den
     evalerr = np.abs(L - Lg) / np.maximum(np.abs(Lg), 1e-3)
-    print("%s: rows %d  e p50 %.2e p99 %.2e max %.2e  loss reached %+.2e  loss eval %.2e"
-          % (name, len(E), np.median(e), np.percentile(e, 99), e.max(), np.abs(reach).max(), evalerr.max()))
-    assert np.percentile(e, 99) <= TOL and e.max() <= 5e-2
+    print("%s: rows %d  e p50 %.2e p99 %.2e max %.2e  after kink excuses max %.2e (%d rows excused)  "
+          "loss reached %+.2e  loss eval %.2e"
+          % (name, len(E), np.median(e), np.percentile(e, 99), e.max(), best.max(), len(notes),
+             np.abs(reach).max(), evalerr.max()))
+    for i, e0, e1, ev in notes:
+        print("   row %d: %.2e from the oracle, %.2e from the trajectory flipped at step %d, layer %d, "
+              "observation %d, unit %d (|z| = %.1e)" % (i, e0, e1, ev[1], ev[2], ev[3], ev[4], ev[0]))
+    assert best.max() <= TOL, "rows beyond %g not explained by a kink decision: %s" % (
+        TOL, np.nonzero(best > TOL)[0].tolist())
     assert np.abs(reach).max() <= 1e-3
     assert evalerr.max() <= TOL
 
@@ -84,7 +123,7 @@ def test_step_counts_and_statuses(ctx):
         E, L, st = run(ctx, S, p, rows.row_ptr, rows.col, rows.val, steps=steps)
         compare("ncf steps=%d" % steps, E, L, st,
                 ncf.foldin(rows.row_ptr, rows.col, rows.val, S, p, steps, C["eta"], C["mu"]), S, p, rows.row_ptr,
-                rows.col, rows.val)
+                rows.col, rows.val, steps=steps)
     # status rows next to good rows of the same wavefront pair (empty | good, bad index | NaN,
     # good | empty)
     rp = np.array([0, 0, 2, 4, 6, 9, 9], dtype=np.int64)
@@ -93,7 +132,8 @@ def test_step_counts_and_statuses(ctx):
     E, L, st = run(ctx, S, p, rp, col, val, steps=10)
     assert st.tolist() == [1, 0, 5, 3, 0, 1]
     assert (E[[0, 2, 3, 5]] == 0).all() and (L[[0, 2, 3, 5]] == 0).all()
-    compare("ncf status rows", E, L, st, ncf.foldin(rp, col, val, S, p, 10, C["eta"], C["mu"]), S, p, rp, col, val)
+    compare("ncf status rows", E, L, st, ncf.foldin(rp, col, val, S, p, 10, C["eta"], C["mu"]), S, p, rp, col, val,
+            steps=10)
 
 
 def test_invalid_arguments(ctx):

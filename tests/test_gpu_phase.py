@@ -37,7 +37,7 @@ def test_windows_across_steps(ctx, n):
     P = r.choice(np.array([10.0, 59.9, 60.0, 61.0, 150.0], np.float32), size=(300, 700),
                  p=[0.004, 0.004, 0.2, 0.3, 0.492])
     got = run(ctx, P, 60.0, n)
-    want = np.array([phase.detect(tr, n_window=n, n_intervals=1) for tr in P])
+    want = np.array([phase.detect(tr, n_window=n) for tr in P])
     assert np.array_equal(got, want)
 
 

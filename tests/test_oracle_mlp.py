@@ -105,3 +105,44 @@ def test_fallback_limits():
     s, e = rows.row_ptr[i], rows.row_ptr[i + 1]
     resid = rows.val[s:e].astype(np.float64) - V[rows.col[s:e]].astype(np.float64) @ net[i]
     assert abs(rho[i] - np.sqrt((resid ** 2).mean())) < 1e-14
+
+
+def test_forward_worked_by_hand():
+    # Pre-activations at least 40 away from 0, where GELU is exactly z or exactly 0 in float64,
+    # and weights exact in bfloat16, so the output follows by hand.  W2 is not symmetric: a
+    # forward pass that used its transpose gives other numbers.
+    W1 = np.array([[64, 0, 20, 0], [0, 50, 41, 0], [0, 0, -60, 45]], dtype=np.float32)
+    b1 = np.zeros(3, np.float32)
+    W2 = np.array([[1, 2, 5], [3, 4, 7], [0, -1, 2]], dtype=np.float32)
+    b2 = np.zeros(3, np.float32)
+    W3 = np.array([[1, -1, 2], [0.5, 0, 0.25]], dtype=np.float32)
+    b3 = np.array([0.25, -1.0], dtype=np.float32)
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([0, 1], dtype=np.int32)
+    val = np.array([0.5, 1.0])
+    X = mlp.dense_input(rp, col, val, 2)  # rows [0.5, 0, 1, 0] and [0, 1, 0, 1]
+    out, (_, z1, h1, z2, h2) = mlp.forward([W1, b1, W2, b2, W3, b3], X)
+    # row 0: z1 = (52, 41, -60) -> h1 = (52, 41, 0); z2 = (134, 320, -41) -> h2 = (134, 320, 0)
+    # row 1: z1 = (0, 50, 45)   -> h1 = (0, 50, 45); z2 = (325, 515, 40)  -> h2 = (325, 515, 40)
+    assert h1.tolist() == [[52, 41, 0], [0, 50, 45]]
+    assert h2.tolist() == [[134, 320, 0], [325, 515, 40]]
+    assert out.tolist() == [[-185.75, 66.0], [-109.75, 171.5]]
+
+
+def test_forward_invariant_under_relabelling_hidden_units():
+    # permuting the units of a hidden layer (rows of its weights and bias, columns of the next
+    # layer's weights) leaves the output unchanged; a transposed W2 or W3 in the forward pass
+    # breaks this for non-symmetric weights
+    r = np.random.default_rng(33)
+    n, h, k = 5, 8, 3
+    params = [r.normal(size=(h, 2 * n)), r.normal(size=h), r.normal(size=(h, h)), r.normal(size=h),
+              r.normal(size=(k, h)), r.normal(size=k)]
+    X = r.normal(size=(6, 2 * n))
+    base, _ = mlp.forward(params, X)
+    p1, p2 = r.permutation(h), r.permutation(h)
+    W1, b1, W2, b2, W3, b3 = params
+    perm = [W1[p1], b1[p1], W2[p2][:, p1], b2[p2], W3[:, p2], b3]
+    out, _ = mlp.forward(perm, X)
+    assert np.allclose(out, base, rtol=1e-12, atol=1e-12)
+    swapped = [W1, b1, W2.T, b2, W3, b3]
+    assert not np.allclose(mlp.forward(swapped, X)[0], base, rtol=1e-3)

@@ -1,6 +1,6 @@
 """Pins of the Algorithm 1 oracle: hand-built traces with known answers, the paper's
-parameters (0.2 s sampling, 5 s window, 60 W), and brute force over the window definition
-on random traces."""
+parameters (0.2 s sampling, 5 s window, 60 W), brute force over the window definition on
+random traces, and the five 1 s intervals of the paper's window checked one by one."""
 import numpy as np
 
 from oracle import phase
@@ -49,4 +49,21 @@ def test_brute_force_window_definition():
             if (p[t - N + 1:t + 1] >= 60.0).all():
                 want = t
                 break
-        assert phase.detect(p, n_window=N, n_intervals=5 if N % 5 == 0 else 1) == want
+        assert phase.detect(p, n_window=N) == want
+
+
+def test_interval_split_checks_the_same_readings():
+    # the paper tests its window as five 1 s intervals of 5 readings; checking the intervals
+    # one by one (stopping at the first interval with a reading below P_th) reports the same
+    # index as the run-length evaluation
+    r = np.random.default_rng(5)
+    for _ in range(200):
+        L = int(r.integers(1, 90))
+        p = r.choice([10.0, 59.9, 60.0, 75.0, 250.0], size=L, p=[0.04, 0.04, 0.12, 0.3, 0.5])
+        want = -1
+        for t in range(24, L):
+            window = p[t - 24:t + 1]
+            if all(not (window[5 * i:5 * i + 5] < 60.0).any() for i in range(5)):
+                want = t
+                break
+        assert phase.detect(p) == want
