@@ -58,6 +58,11 @@ __device__ __forceinline__ float bload_f32(__amdgpu_buffer_rsrc_t r, int off_byt
 __device__ __forceinline__ int bload_i32(__amdgpu_buffer_rsrc_t r, int off_bytes) {
   return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off_bytes, 0, 0);
 }
+// Value of x in lane `l` (a wave-uniform lane).  The builtin takes and returns int, so a
+// float goes through its bits: passed as a float it would be converted to an integer value.
+__device__ __forceinline__ float readlane_f32(float x, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
 __device__ __forceinline__ f4 bload_f4(__amdgpu_buffer_rsrc_t r, int off_bytes) {
   return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off_bytes, 0, 0));
 }

@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(int64_t m, const int64_t *
           for (int e = 0; e < 8; ++e) {
             const int t = u0 + e < nb ? u0 + e : nb - 1;
             jj[e] = __builtin_amdgcn_readlane(jl, t);
-            rr[e] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, rl), t));
+            rr[e] = readlane_f32(rl, t);
             const int js = (jj[e] >= 0 && jj[e] < n) ? jj[e] : 0;
             wa[e] = *reinterpret_cast<const uint2 *>(W1T + (int64_t)js * 256 + 4 * lane);
             wm[e] = *reinterpret_cast<const uint2 *>(W1T + (int64_t)(n + js) * 256 + 4 * lane);

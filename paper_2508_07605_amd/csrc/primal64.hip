@@ -168,7 +168,7 @@ __global__ __launch_bounds__(64 * kP64Waves) __attribute__((amdgpu_waves_per_eu(
         constexpr int r = decltype(R)::value;
         a[r] = __builtin_fmaf(-gcol[r], lc, a[r]);
       });
-      const float bp = __builtin_amdgcn_readlane(b, p);  // y_p, final at step p
+      const float bp = readlane_f32(b, p);  // y_p, final at step p
       b = __builtin_fmaf(-lc, bp, b);
       dd = me == p ? dp : dd;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(64 * kP64Waves) __attribute__((amdgpu_waves_per_eu(
     sfor_down<0, 64>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
       asm volatile("" : "+v"(me));
-      const float xp = __builtin_amdgcn_readlane(b * rd, p);
+      const float xp = readlane_f32(b * rd, p);
       b = me < p ? __builtin_fmaf(-a[p], xp, b) : b;
     });
     const float x = b * rd;
