@@ -107,6 +107,24 @@ open_status open_foldin_graph(open_ctx *ctx, const float *F, int32_t n, int32_t 
                               int32_t weighted, float *U_out, int32_t *row_status);
 
 /*
+ * Allocation-free fold-in, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, same
+ * kernels and the same result as open_foldin, bit for bit, but the bucketing buffers live in
+ * a static device array of the library (about 16 MiB per GPU, held until the process ends)
+ * instead of context workspaces, so the call allocates nothing, frees nothing and never waits
+ * on the host.
+ *   Limits: m <= open_foldin_noalloc_max_rows() (1,048,576) rows per call, else
+ *   OPEN_E_INVALID; n < 1024 factor rows (no split-K rows), else OPEN_E_UNSUPPORTED.
+ *   Sharing: every call on one GPU uses that GPU's one array, which keeps the last call's
+ *   contents (each call writes every element it reads).  Calls that overlap in time on one
+ *   GPU (other streams, other contexts, other host threads) race; serialize them.
+ */
+open_status open_foldin_noalloc(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m,
+                                const int64_t *row_ptr, const int32_t *col, const float *val, float lambda,
+                                int32_t weighted, float *U_out, int32_t *row_status);
+int64_t open_foldin_noalloc_max_rows(void);
+
+/*
  * Phase-transition detection (Algorithm 1, Section III-B.2) for T power traces at once.
  * Trace t is power[t*ld .. t*ld + L) (device float32, GPU power readings in W at a fixed
  * sampling interval).  first_index[t] (device int64) receives the 0-based index of the

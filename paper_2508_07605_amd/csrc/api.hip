@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <functional>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -13,6 +14,35 @@
 #include "rowsolve.h"
 
 namespace openk {
+
+// ---- static scratch of the allocation-free fold-in (one copy per GPU, held until the process
+// ends).  Layout: the bucketed row list, then the per-block class counts, then the class table.
+constexpr int64_t kNoAllocMaxRows = int64_t(1) << 20;
+constexpr size_t kScrList = 0;
+constexpr size_t kScrHist = kScrList + sizeof(RowRef) * (size_t)kNoAllocMaxRows;
+constexpr size_t kScrCls = kScrHist + ((sizeof(int32_t) * (size_t)kNumClasses * (size_t)(kNoAllocMaxRows / 4096) + 255) &
+                                       ~(size_t)255);
+constexpr size_t kScrBytes = kScrCls + sizeof(int64_t) * 2 * kNumClasses;
+static __device__ __align__(256) unsigned char scratch[kScrBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up once per device with the device
+// current.  The array's name in host code is not a device address.
+static hipError_t scratch_address(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_addr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 open_status ws_get(open_ctx *ctx, int slot, size_t bytes, void **out) {
   if (bytes == 0) bytes = 16;
@@ -141,6 +171,11 @@ open_status open_create(open_ctx **out, int device, void *hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->num_cu = prop.multiProcessorCount;
+  if (scratch_address(device, &ctx->scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return OPEN_E_DEVICE;
+  }
   *out = ctx;
   return OPEN_OK;
 }
@@ -304,6 +339,36 @@ open_status open_foldin_graph(open_ctx *ctx, const float *F, int32_t n, int32_t 
   memcpy(&ctx->gkey, &key, sizeof(key));  // byte copy: the key is compared with memcmp
   return OPEN_OK;
 }
+
+open_status open_foldin_noalloc(open_ctx *ctx, const float *F, int32_t n, int32_t k, int64_t m,
+                                const int64_t *row_ptr, const int32_t *col, const float *val, float lambda,
+                                int32_t weighted, float *U_out, int32_t *row_status) {
+  if (!ctx) return OPEN_E_INVALID;
+  if (!rank_ok(k)) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
+  if (n <= 0 || !F) return fail(ctx, OPEN_E_INVALID, "factor matrix must be non-empty");
+  if (n >= kSplitMin)
+    return fail(ctx, OPEN_E_UNSUPPORTED, "the allocation-free fold-in needs fewer than 1024 factor rows");
+  if (!(lambda >= 0.0f) || !isfinite(lambda)) return fail(ctx, OPEN_E_INVALID, "lambda must be finite and >= 0");
+  open_status st = check_csr(ctx, m, row_ptr, col, val);
+  if (st) return st;
+  if (m > kNoAllocMaxRows)
+    return fail(ctx, OPEN_E_INVALID, "the allocation-free fold-in takes at most " + std::to_string(kNoAllocMaxRows) +
+                                         " rows per call (got " + std::to_string(m) + ")");
+  if (m > 0 && !U_out) return fail(ctx, OPEN_E_INVALID, "output must not be NULL");
+  if (!ctx->scratch) return fail(ctx, OPEN_E_DEVICE, "scratch address unknown");
+  if (sizeof(int32_t) * (size_t)bucket_hist_ints(m) > kScrCls - kScrHist)
+    return fail(ctx, OPEN_E_INVALID, "row count exceeds the scratch layout");
+  if (m == 0) return OPEN_OK;
+  OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  unsigned char *base = (unsigned char *)ctx->scratch;
+  RowRef *list = (RowRef *)(base + kScrList);
+  int32_t *hist = (int32_t *)(base + kScrHist);
+  int64_t *cls = (int64_t *)(base + kScrCls);
+  if ((st = bucket_rows_into(ctx, m, row_ptr, k, hist, list, cls, INT64_MAX))) return st;
+  return rowsolve_launch(ctx, F, n, k, row_ptr, col, val, lambda, weighted, list, cls, U_out, row_status, m);
+}
+
+int64_t open_foldin_noalloc_max_rows(void) { return kNoAllocMaxRows; }
 
 int32_t open_tune_info(int32_t k, const char **names, int32_t *nvar, int32_t max) {
   int ng = 0;

@@ -223,29 +223,40 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
     pos += add;
   }
 }
-open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, RowRef **list, int64_t **cls,
-                        int64_t split_min, const uint8_t *mask) {
+open_status bucket_rows_into(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t *hist, RowRef *list,
+                             int64_t *cls, int64_t split_min, const uint8_t *mask) {
   const int nblk = (int)((m + kRowsPerBlock - 1) / kRowsPerBlock);
-  void *hist = nullptr, *lst = nullptr, *c = nullptr;
-  open_status st;
-  if ((st = ws_get(ctx, open_ctx::WS_HIST, sizeof(int32_t) * (size_t)kNumClasses * (nblk > 0 ? nblk : 1), &hist)))
-    return st;
-  if ((st = ws_get(ctx, open_ctx::WS_LIST, sizeof(RowRef) * (size_t)(m > 0 ? m : 1), &lst))) return st;
-  if ((st = ws_get(ctx, open_ctx::WS_CLS, sizeof(int64_t) * 2 * kNumClasses, &c))) return st;
   if (m > 0) {
     OPEN_LAUNCH(ctx, "bucket_count", k_class_count, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask, k,
-                split_min, (int32_t *)hist);
+                split_min, hist);
   }
   if (m > 0 && nblk <= kSelfScanMaxBlocks) {
     OPEN_LAUNCH(ctx, "bucket_place", k_class_place<true>, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask,
-                k, split_min, (const int32_t *)hist, (RowRef *)lst, (int64_t *)c);
+                k, split_min, (const int32_t *)hist, list, cls);
   } else {
-    OPEN_LAUNCH(ctx, "bucket_scan", k_class_scan, dim3(1), dim3(1024), 0, (int32_t *)hist, nblk, (int64_t *)c);
+    OPEN_LAUNCH(ctx, "bucket_scan", k_class_scan, dim3(1), dim3(1024), 0, hist, nblk, cls);
     if (m > 0) {
       OPEN_LAUNCH(ctx, "bucket_place", k_class_place<false>, dim3(nblk), dim3(kBucketThreads), 0, m, row_ptr, mask,
-                  k, split_min, (const int32_t *)hist, (RowRef *)lst, (int64_t *)c);
+                  k, split_min, (const int32_t *)hist, list, cls);
     }
   }
+  return OPEN_OK;
+}
+
+int64_t bucket_hist_ints(int64_t m) {
+  const int64_t nblk = (m + kRowsPerBlock - 1) / kRowsPerBlock;
+  return (int64_t)kNumClasses * (nblk > 0 ? nblk : 1);
+}
+
+open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, RowRef **list, int64_t **cls,
+                        int64_t split_min, const uint8_t *mask) {
+  void *hist = nullptr, *lst = nullptr, *c = nullptr;
+  open_status st;
+  if ((st = ws_get(ctx, open_ctx::WS_HIST, sizeof(int32_t) * (size_t)bucket_hist_ints(m), &hist))) return st;
+  if ((st = ws_get(ctx, open_ctx::WS_LIST, sizeof(RowRef) * (size_t)(m > 0 ? m : 1), &lst))) return st;
+  if ((st = ws_get(ctx, open_ctx::WS_CLS, sizeof(int64_t) * 2 * kNumClasses, &c))) return st;
+  if ((st = bucket_rows_into(ctx, m, row_ptr, k, (int32_t *)hist, (RowRef *)lst, (int64_t *)c, split_min, mask)))
+    return st;
   *list = (RowRef *)lst;
   *cls = (int64_t *)c;
   return OPEN_OK;

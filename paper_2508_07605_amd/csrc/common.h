@@ -123,6 +123,8 @@ struct open_ctx {
   size_t ws_bytes[WS_COUNT] = {};
   // bumped whenever a workspace is reallocated: a recorded graph holds the old addresses
   uint64_t ws_gen = 0;
+  // this device's copy of the library's static scratch array (allocation-free fold-in)
+  void *scratch = nullptr;
   // chosen kernel variant of each size-class group, per rank (8, 16, 32, 64); 0 = default
   int8_t tune[4][16] = {};
   // graph capture: while capturing, launches go to cap_stream and nothing may allocate or sync
@@ -210,6 +212,11 @@ constexpr int kSplitClass = 16;  // rows solved by the split-K path
 constexpr int64_t kSplitMin = 1024;  // observations from which a row takes the split-K path
 open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, RowRef **list, int64_t **cls,
                         int64_t split_min, const uint8_t *mask = nullptr);
+// The same into caller-provided buffers: hist of bucket_hist_ints(m) ints, list of m entries,
+// cls of 2 * kNumClasses.  Every element that is read is written first (no clearing needed).
+open_status bucket_rows_into(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t *hist, RowRef *list,
+                             int64_t *cls, int64_t split_min, const uint8_t *mask = nullptr);
+int64_t bucket_hist_ints(int64_t m);
 // Column view on the device (stable counting sort); entries with a column outside [0, n) are dropped.
 open_status csr_to_csc_dev(open_ctx *ctx, int64_t m, int n, const int64_t *row_ptr, const int32_t *col,
                            const float *val, int64_t *col_ptr, int32_t *row_idx, float *cval);

@@ -34,6 +34,8 @@ SIGNATURES = {
     "open_profile_read": (_I32, [_P, _P, _P, _P, _I32, _I32]),
     "open_foldin": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
     "open_foldin_graph": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
+    "open_foldin_noalloc": (_I32, [_P, _P, _I32, _I32, _I64, _P, _P, _P, _F32, _I32, _P, _P]),
+    "open_foldin_noalloc_max_rows": (_I64, []),
     "open_phase_detect": (_I32, [_P, _P, _I64, _I64, _I64, _F32, _I32, _P]),
     "open_perf_predict": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "open_ncf_foldin": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _I32, _F32, _F32, _P,
@@ -189,6 +191,19 @@ def open_foldin_graph(ctx, F, row_ptr, col, val, lam, weighted=True, U_out=None,
                                       _dev(val, torch.float32, "val"), float(lam), int(bool(weighted)),
                                       _dev(U_out, torch.float32, "U_out", m * k),
                                       _dev(row_status, torch.int32, "row_status", m)))
+    return U_out
+
+
+def open_foldin_noalloc(ctx, F, row_ptr, col, val, lam, weighted, U_out, row_status=None):
+    """open_foldin with the library's static scratch array instead of context workspaces (the
+    caller provides the output; nothing is allocated)."""
+    n, k = F.shape
+    m = row_ptr.numel() - 1
+    ctx.check(lib().open_foldin_noalloc(ctx.handle, _dev(F, torch.float32, "F"), n, k, m,
+                                        _dev(row_ptr, torch.int64, "row_ptr", m + 1), _dev(col, torch.int32, "col"),
+                                        _dev(val, torch.float32, "val"), float(lam), int(bool(weighted)),
+                                        _dev(U_out, torch.float32, "U_out", m * k),
+                                        _dev(row_status, torch.int32, "row_status", m)))
     return U_out
 
 
