@@ -82,10 +82,11 @@ def recorded_traffic(kernel, choice):
     return by_choice.get(str(choice), rec["traffic_bytes_per_launch"])
 
 
-def surrogate_leg(args, ctx, dV, drp, dcol, dval, m, steps, warmup, log):
-    """Surrogate fold-in (MLP + ALS fallback on rows whose observed-entry RMS residual exceeds
-    tau): train on 2M ALS fold-in targets of new draws, then time surrogate+fallback on the
-    benchmark rows, and the same with an untrained network (which falls back almost everywhere)."""
+def surrogate_leg(args, ctx, dV, drp, dcol, dval, m, steps, warmup, log, als_ms):
+    """Surrogate fold-in (MLP + ridge fallback on rows whose observed-entry RMS residual exceeds
+    tau): train through open_mlp_train on the ALS fold-ins of 2M new draws, then time
+    surrogate+fallback on the benchmark rows, beside the same with the untrained network (same
+    seeded initial weights), which falls back almost everywhere, and the plain ALS fold-in."""
     import numpy as np
     import torch
 
@@ -93,70 +94,77 @@ def surrogate_leg(args, ctx, dV, drp, dcol, dval, m, steps, warmup, log):
 
     c = synth.CONFIGS["surrogate"]
     grid = synth.grid_of("surrogate")
-    n, k, lam, tau = grid.n, c["k"], c["lam"], c["tau"]
+    n, k, lam, wt, tau = grid.n, c["k"], c["lam"], c["weighted"], c["tau"]
     dev = dV.device
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     t0 = time.time()
     tr = synth.draw_rows(c["cfg_id"], grid, c["m_train"], c["counts"], seed=c["train_seed"])
     trp, tcol, tval = to(tr.row_ptr), to(tr.col), to(tr.val)
-    target = native.open_foldin(ctx, dV, trp, tcol, tval, lam, True)
+    target = native.open_foldin(ctx, dV, trp, tcol, tval, lam, wt)
     torch.cuda.synchronize()
     log("surrogate: %d training rows and their ALS targets in %.1f s" % (tr.m, time.time() - t0))
 
-    init = np.concatenate([np.asarray(p, np.float32).reshape(-1)
-                           for p in synth.mlp_init(c["cfg_id"], (2 * n, c["hidden"], c["hidden"], k), seed=1)])
-    net = native.Surrogate(ctx, n, k, c["hidden"], init=init)
-    untrained = native.Surrogate(ctx, n, k, c["hidden"], init=init)
-    B = c["batch"]
-    per_epoch = (tr.m + B - 1) // B
-    total = int(round(args.surrogate_epochs * per_epoch))
-    gen = torch.Generator(device=dev).manual_seed(7)
-    loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    hist = []
+    net = native.Surrogate(ctx, n, k, c["hidden"], seed=1)
+    untrained = native.Surrogate(ctx, n, k, c["hidden"], seed=1)
+    B, E = c["batch"], int(args.surrogate_epochs)
     torch.cuda.synchronize()
     t0 = time.time()
-    done = 0
-    while done < total:
-        perm = torch.randperm(tr.m, generator=gen, device=dev)
-        for b in range(per_epoch):
-            if done == total:
-                break
-            net.train_step(trp, tcol, tval, target, perm[b * B:(b + 1) * B], c["lr"], loss_out=loss)
-            done += 1
-            if done % 100 == 0 or done == total:
-                hist.append((done, float(loss.item())))
+    hist = net.train(trp, tcol, tval, target, B, c["lr"], E, seed=7)
     torch.cuda.synchronize()
     train_s = time.time() - t0
-    log("surrogate: %d Adam steps (%.2f epochs) in %.1f s, loss %s" % (total, total / per_epoch, train_s,
-                                                                     hist[::max(1, len(hist) // 6)] + hist[-1:]))
+    n_steps = E * (tr.m // B)
+    log("surrogate: %d epochs (%d Adam steps) in %.2f s, %.3f ms per step; epoch losses %s"
+        % (E, n_steps, train_s, 1e3 * train_s / max(n_steps, 1), np.array2string(hist, precision=3)))
     del trp, tcol, tval, target
 
     U = torch.empty((m, k), dtype=torch.float32, device=dev)
     used = torch.empty(m, dtype=torch.uint8, device=dev)
+    rho = torch.empty(m, dtype=torch.float32, device=dev)
 
     def timed(model):
         for _ in range(warmup):
-            model.foldin(dV, drp, dcol, dval, tau, lam, True, U_out=U, used_fallback=used, count=False)
+            model.foldin(dV, drp, dcol, dval, tau, lam, wt, U_out=U, used_fallback=used, count=False)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            model.foldin(dV, drp, dcol, dval, tau, lam, True, U_out=U, used_fallback=used, count=False)
+            model.foldin(dV, drp, dcol, dval, tau, lam, wt, U_out=U, used_fallback=used, count=False)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        _, nf = model.foldin(dV, drp, dcol, dval, tau, lam, True, U_out=U, used_fallback=used)
+        _, nf = model.foldin(dV, drp, dcol, dval, tau, lam, wt, U_out=U, used_fallback=used, rho=rho)
         return ms, nf
 
     ms0, nf0 = timed(untrained)
     ms, nf = timed(net)
+    # the floor of any network that reproduces the ALS fold-in: rows whose own ALS residual is above tau
+    Ua = native.open_foldin(ctx, dV, drp, dcol, dval, lam, wt)
+    ra = native.open_residual(ctx, drp, dcol, dval, Ua, dV)
+    als_above = float((ra > tau).float().mean().item())
+    del Ua, ra
+    ctx.profile(True)
+    net.foldin(dV, drp, dcol, dval, tau, lam, wt, U_out=U, used_fallback=used, count=False)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    infer_ms = prof["mlp_infer"][0] if "mlp_infer" in prof else None
+    flops = (2.0 * 256 * 2 * float(drp[-1].item()) + m * 2.0 * (256 * 256 + 256 * k))
     out = {
+        "workload": "surrogate fold-in + ridge fallback: the %d benchmark rows, network %d-%d-%d-%d trained "
+                    "%d epochs on %d ALS fold-ins, tau %g, plain lambda %g" % (m, 2 * n, c["hidden"], c["hidden"], k,
+                                                                          E, tr.m, tau, lam),
         "rows_per_s": m / (ms * 1e-3), "ms_per_step": ms, "fallback_fraction": nf / m,
         "untrained_rows_per_s": m / (ms0 * 1e-3), "untrained_fallback_fraction": nf0 / m,
-        "train_steps": total, "train_epochs": round(total / per_epoch, 3), "train_rows": tr.m, "batch": B,
-        "train_seconds": round(train_s, 2), "final_loss": hist[-1][1] if hist else None, "tau": tau,
+        "als_rows_per_s": m / (als_ms * 1e-3), "als_residual_above_tau_fraction": als_above,
+        "train_steps": n_steps, "train_epochs": E, "train_rows": tr.m, "batch": B,
+        "train_seconds": round(train_s, 3), "train_ms_per_step": round(1e3 * train_s / max(n_steps, 1), 4),
+        "epoch_loss": [float(x) for x in hist], "tau": tau,
         "network": "%d-%d-%d-%d bf16 weights, fp32 accumulate" % (2 * n, c["hidden"], c["hidden"], k),
     }
+    if infer_ms:
+        tf = flops / (infer_ms * 1e-3) / 1e12
+        out["infer_roofline"] = {"kernel": "mlp_infer", "kernel_ms": round(infer_ms, 4), "bound": "mfma",
+                                 "achieved": round(tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(tf / PEAK_BF16_TFLOPS, 4), "algorithmic_flops": flops}
     untrained.close()
     net.close()
     return out, U
@@ -438,7 +446,7 @@ def main():
     ap.add_argument("--no-predictor", action="store_true", help="skip the offline performance predictor leg")
     ap.add_argument("--no-ncf", action="store_true", help="skip the NCF fold-in leg")
     ap.add_argument("--fit-sweeps", type=int, default=3, help="timed ALS sweeps in the fit leg")
-    ap.add_argument("--surrogate-epochs", type=float, default=2.0,
+    ap.add_argument("--surrogate-epochs", type=int, default=10,
                     help="training epochs over the 2M ALS fold-in targets (batch 4096, Adam 1e-3)")
     ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuned kernel variants")
     args = ap.parse_args()
@@ -454,7 +462,7 @@ def main():
     from paper_2508_07605_amd import autotune, native, synth
 
     cfg = synth.CONFIGS["foldin"]
-    k, lam = cfg["k"], cfg["lam"]
+    k, lam, wt = cfg["k"], cfg["lam"], cfg["weighted"]
     m = args.rows or cfg["m"]
     grid = synth.grid_of("foldin")
     t0 = time.time()
@@ -470,10 +478,10 @@ def main():
     ctx = native.Context(0)
 
     def step_eager():
-        native.open_foldin(ctx, dV, drp, dcol, dval, lam, True, U_out=dU, row_status=dst)
+        native.open_foldin(ctx, dV, drp, dcol, dval, lam, wt, U_out=dU, row_status=dst)
 
     def step_graph():
-        native.open_foldin_graph(ctx, dV, drp, dcol, dval, lam, True, U_out=dU, row_status=dst)
+        native.open_foldin_graph(ctx, dV, drp, dcol, dval, lam, wt, U_out=dU, row_status=dst)
 
     step = step_graph if args.graph else step_eager
 
@@ -490,7 +498,7 @@ def main():
     tune_table = None
     if not args.no_autotune:
         t0 = time.time()
-        _, tune_table = autotune.tune(ctx, dV, drp, dcol, dval, lam, True, reps=3, path=args.tune_cache)
+        _, tune_table = autotune.tune(ctx, dV, drp, dcol, dval, lam, wt, reps=3, path=args.tune_cache)
         print("bench: autotune %.1f s, variants %s, ms %s" % (time.time() - t0, ctx.tune_get(k), tune_table),
               file=sys.stderr, flush=True)
     variants = dict(zip([g for g, _ in native.open_tune_info(k)], ctx.tune_get(k)))
@@ -563,7 +571,7 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched ALS fold-in: %d new apps x 480 settings (24 CPU x 20 GPU caps), "
-                               "4-24 observed per app, rank 32, weighted lambda 0.05, fixed float32 setting factors"
+                               "4-24 observed per app, rank 32, plain lambda 0.05, fixed float32 setting factors"
                                % m, "rows": m, "settings": grid.n, "rank": k, "nnz": rows.nnz,
                    "parallelism": "single GPU", "kernel_variants": variants},
         "pass_tflops": round(pass_tflops, 3),
@@ -599,7 +607,7 @@ def main():
     U_sur = None
     if not args.no_surrogate:
         log = lambda msg: print("bench: " + msg, file=sys.stderr, flush=True)
-        sur, U_sur = surrogate_leg(args, ctx, dV, drp, dcol, dval, m, args.steps, args.warmup, log)
+        sur, U_sur = surrogate_leg(args, ctx, dV, drp, dcol, dval, m, args.steps, args.warmup, log, ms)
         out["surrogate"] = sur
         log("surrogate+fallback %.3e rows/s (fallback %.3f), untrained %.3e rows/s (fallback %.3f)"
             % (sur["rows_per_s"], sur["fallback_fraction"], sur["untrained_rows_per_s"],
@@ -612,15 +620,35 @@ def main():
         rs = np.random.default_rng(2025)
         probe = np.sort(rs.choice(m, size=min(m, 20_000), replace=False))
         t1 = time.perf_counter()
-        oracle.ridge_subset(probe, rows.row_ptr, rows.col, rows.val, V, lam, True)
+        oracle.ridge_subset(probe, rows.row_ptr, rows.col, rows.val, V, lam, wt)
         per_row = (time.perf_counter() - t1) / len(probe)
         ns = int(min(m, max(len(probe), args.cpu_seconds / max(per_row, 1e-9))))
         sample = np.sort(rs.choice(m, size=ns, replace=False))
         t1 = time.perf_counter()
-        Uref, st_ref = oracle.ridge_subset(sample, rows.row_ptr, rows.col, rows.val, V, lam, True)
+        Uref, st_ref = oracle.ridge_subset(sample, rows.row_ptr, rows.col, rows.val, V, lam, wt)
         cpu_s = time.perf_counter() - t1
+        # one thread on a smaller sample
+        one = sample[:max(1, min(ns, int(args.cpu_seconds / 4 / max(per_row * threads, 1e-9))))]
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        oracle.ridge_subset(one, rows.row_ptr, rows.col, rows.val, V, lam, wt)
+        cpu1_s = time.perf_counter() - t1
+        oracle.set_threads(threads)
+        cpu_model = None
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": ns / cpu_s, "unit": "rows/s", "cores": threads, "kind": "oracle",
-                               "sample": "%d of the %d rows (seeded), FP64 primal ridge solves, %.1f s" % (ns, m, cpu_s)}
+                               "sample": "%d of the %d rows (seeded), FP64 primal ridge solves, %.1f s"
+                                         % (ns, m, cpu_s),
+                               "single_thread": {"value": len(one) / cpu1_s, "unit": "rows/s", "cores": 1,
+                                                 "sample": "the first %d rows of that sample, %.1f s"
+                                                           % (len(one), cpu1_s)},
+                               "cpu_model": cpu_model, "host_cpus": os.cpu_count()}
         ev = sample[:20_000]
         Ug = dU[torch.from_numpy(ev).to(dev)].cpu().numpy().astype(np.float64)
         Uo = Uref[:len(ev)]
@@ -632,6 +660,9 @@ def main():
         Vd = V.astype(np.float64)
         rmse_g = float(np.sqrt((((Ug @ Vd.T) - T)[~obs] ** 2).mean()))
         rmse_o = float(np.sqrt((((Uo @ Vd.T) - T)[~obs] ** 2).mean()))
+        # the other lambda convention (lambda n_i), for the reading of the fold-in's regulariser
+        Uw, _ = oracle.ridge_subset(ev, rows.row_ptr, rows.col, rows.val, V, lam, not wt)
+        rmse_w = float(np.sqrt((((Uw @ Vd.T) - T)[~obs] ** 2).mean()))
         e = np.linalg.norm(Ug - Uo, axis=1) / np.linalg.norm(Uo, axis=1)
         if U_sur is not None:
             Us = U_sur[torch.from_numpy(ev).to(dev)].cpu().numpy().astype(np.float64)
@@ -641,6 +672,7 @@ def main():
                                                                               .mean()))})
         out["accuracy"] = {"rows": len(ev), "rmse_gpu": rmse_g, "rmse_oracle": rmse_o,
                            "rmse_gap": abs(rmse_g - rmse_o), "max_rel_err_vs_oracle": float(e.max()),
+                           ("rmse_oracle_weighted_lambda" if not wt else "rmse_oracle_plain_lambda"): rmse_w,
                            "accuracy_pct_1_minus_mape": float(100 * (1 - np.abs(((Ug @ Vd.T) - T)[~obs] /
                                                                                T[~obs]).mean()))}
     print(json.dumps(out), flush=True)

@@ -241,8 +241,12 @@ open_status open_predict(open_ctx *ctx, const float *U, int64_t m, const float *
  *   W1[hidden][2n], b1[hidden], W2[hidden][hidden], b2[hidden], W3[k][hidden], b3[k].
  * hidden must be 256; n at most 4096.
  */
+/* init_host: HOST float32 weights in that packing, or NULL for seeded weights: every weight
+ * and bias of a layer with fan-in f uniform on [-1/sqrt f, 1/sqrt f), parameter e of the
+ * flat vector drawn as (mix64(seed ^ mix64(e)) >> 40) * 2^-24 in [0, 1), mix64 being the
+ * SplitMix64 output function (Steele, Lea and Flood 2014). */
 open_status open_mlp_create(open_ctx *ctx, open_mlp **mlp, int32_t n, int32_t k, int32_t hidden,
-                            const float *init_host);
+                            const float *init_host, uint64_t seed);
 open_status open_mlp_destroy(open_mlp *mlp);
 /* Number of float32 parameters in the packing above. */
 int64_t open_mlp_num_params(int32_t n, int32_t k, int32_t hidden);
@@ -267,6 +271,19 @@ open_status open_mlp_loss_grad(open_mlp *mlp, int64_t m, const int64_t *row_ptr,
 open_status open_mlp_train_step(open_mlp *mlp, int64_t m, const int64_t *row_ptr, const int32_t *col,
                                 const float *val, const float *target, const int64_t *rows, int32_t batch,
                                 float lr, float *loss_out);
+
+/* Training: `epochs` passes over the m CSR rows with their targets (device float32[m*k]), each
+ * epoch in a new seeded order, m / batch full batches per epoch (the remainder waits for a
+ * later order), one Adam step per batch exactly as open_mlp_train_step takes it.  The order of
+ * epoch e is a permutation computed on the device: a four-round Feistel network on 2h-bit
+ * integers (4^h >= m), round keys mix64(mix64(seed) + 4e + r), round function mix64(R ^ key)
+ * masked to h bits, walked along its cycle until the value is below m.  The first step runs
+ * eagerly and the step sequence is then replayed as one recorded HIP graph.  loss_hist: HOST
+ * float32[epochs] or NULL, the mean batch loss of each epoch.  Synchronous.
+ * batch in [1, min(16384, m)]; epochs >= 0; lr finite and > 0. */
+open_status open_mlp_train(open_mlp *mlp, int64_t m, const int64_t *row_ptr, const int32_t *col, const float *val,
+                           const float *target, int32_t batch, float lr, int32_t epochs, uint64_t seed,
+                           float *loss_hist);
 
 /* Surrogate fold-in with ridge fallback: u_i = network output unless its observed-entry RMS
  * residual against the setting factors F exceeds tau, in which case u_i is the ridge

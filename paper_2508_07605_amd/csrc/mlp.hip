@@ -12,6 +12,7 @@
 // accumulation through one tiled GEMM kernel whose epilogue adds the bias and applies GELU,
 // or multiplies by GELU'(z) in the backward pass.  The sparse W1 gradient is accumulated per
 // input feature over a column view of the batch, in a fixed order (no float atomics).
+#include <limits.h>
 #include <math.h>
 #include <string.h>
 
@@ -52,12 +53,78 @@ __device__ __forceinline__ float gelu_grad(float z) {
 }
 
 // ---------------------------------------------------------------- bfloat16 weight copies
-// W1T[j][h] = bf16(W1[h][j]) (2n x H);  Wb[i] = bf16(W[i]) for W2 and W3 (row-major as given)
-__global__ void k_pack_w1t(const float *__restrict__ W1, int H, int twon, uint16_t *__restrict__ W1T) {
-  const int64_t total = (int64_t)H * twon;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// First-layer weights as one 32-bit pair per (setting j, hidden unit h): low half
+// bf16(W1[h][j]) (the weight of the value r_j), high half bf16(W1[h][n + j]) (the weight of the
+// mask bit).  A lane's four units of one setting are one 16-byte load.
+__global__ void k_pack_w1p(const float *__restrict__ W1, int H, int n, uint32_t *__restrict__ W1P) {
+  const int64_t total = (int64_t)H * n, twon = 2 * (int64_t)n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = e / H, h = e % H;
-    W1T[e] = f2bf(W1[h * twon + j]);
+    W1P[e] = (uint32_t)f2bf(W1[h * twon + j]) | ((uint32_t)f2bf(W1[h * twon + n + j]) << 16);
+  }
+}
+
+// W2 as the B operands of the inference kernel's second layer: entry ((w*2 + cb)*16 + ks)*64 +
+// lane (lane = 32 g + i) holds W2[64w + 32cb + i][16ks + 8g .. +8] as 8 bfloat16.
+__global__ void k_pack_w2p(const float *__restrict__ W2, uint4 *__restrict__ W2P) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 8192) return;
+  const int lane = e & 63, ks = (e >> 6) & 15, cb = (e >> 10) & 1, w = e >> 11;
+  const int i = lane & 31, g = lane >> 5;
+  const float *src = W2 + (int64_t)(64 * w + 32 * cb + i) * 256 + 16 * ks + 8 * g;
+  uint32_t pk[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) pk[q] = (uint32_t)f2bf(src[2 * q]) | ((uint32_t)f2bf(src[2 * q + 1]) << 16);
+  W2P[e] = uint4{pk[0], pk[1], pk[2], pk[3]};
+}
+
+// W3 (K x 256) as the B operands of the inference kernel's output layer: entry
+// (cb*16 + ks)*64 + lane (lane = 32 g + i) holds W3[32cb + i][16ks + 8g .. +8] as 8 bfloat16,
+// zero for output rows past K.
+__global__ void k_pack_w3p(const float *__restrict__ W3, int K, uint4 *__restrict__ W3P) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cbs = (K + 31) / 32;
+  if (e >= cbs * 1024) return;
+  const int lane = e & 63, ks = (e >> 6) & 15, cb = e >> 10;
+  const int o = 32 * cb + (lane & 31), g = lane >> 5;
+  uint32_t pk[4] = {0, 0, 0, 0};
+  if (o < K) {
+    const float *src = W3 + (int64_t)o * 256 + 16 * ks + 8 * g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pk[q] = (uint32_t)f2bf(src[2 * q]) | ((uint32_t)f2bf(src[2 * q + 1]) << 16);
+  }
+  W3P[e] = uint4{pk[0], pk[1], pk[2], pk[3]};
+}
+
+// The value r of an observed entry as two bfloat16 parts, r = hi + lo to within 2^-17 |r|, in
+// the pairs (hi, 1) and (lo, 0) that multiply a weight pair (value weight, mask weight).  An
+// entry whose column is outside [0, n) takes the pairs (0, 0), (0, 0): it adds nothing.
+__device__ __forceinline__ void value_pairs(float r, bool valid, uint32_t &p1, uint32_t &p2) {
+  const uint16_t hi = f2bf(r);
+  const uint16_t lo = f2bf(r - bf2f(hi));
+  p1 = valid ? ((uint32_t)hi | (0x3f80u << 16)) : 0u;
+  p2 = valid ? (uint32_t)lo : 0u;
+}
+
+// The lane's weight pairs of setting j (four units, 16 bytes) from the packed first layer
+// through a buffer resource over n settings: j outside [0, n) reads zeros.
+__device__ __forceinline__ uint4 w1_pairs(__amdgpu_buffer_rsrc_t rs, int j, int lane) {
+  const uint32_t off = ((uint32_t)j << 10) + 16u * (uint32_t)lane;  // j = -1 wraps out of range
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+}
+
+// z += a r + c for the lane's four units (w: their weight pairs), as two bfloat16 dot products
+// per unit with float32 accumulation: (a, c).(hi, 1), then (a, c).(lo, 0).  Every first-layer
+// evaluation (training and inference) takes exactly these steps in the row's entry order.
+__device__ __forceinline__ void layer1_step(f4 &z, uint4 w, uint32_t p1, uint32_t p2) {
+  const bf16x2 y1 = __builtin_bit_cast(bf16x2, p1), y2 = __builtin_bit_cast(bf16x2, p2);
+  const uint32_t wq[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    z[q] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, wq[q]), y1, z[q], false);
+    z[q] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, wq[q]), y2, z[q], false);
   }
 }
 
@@ -67,23 +134,20 @@ __global__ void k_pack_w1t(const float *__restrict__ W1, int H, int twon, uint16
 __global__ __launch_bounds__(256) void k_layer1(int64_t B, const int64_t *__restrict__ rows,
                                                 const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                                 const float *__restrict__ val, int n,
-                                                const uint16_t *__restrict__ W1T, const float *__restrict__ b1,
+                                                const uint32_t *__restrict__ W1P, const float *__restrict__ b1,
                                                 float *__restrict__ z1, float *__restrict__ h1) {
   const int lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(W1P, (uint64_t)n * 1024);
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < B; b += nw) {
     const int64_t i = rows ? rows[b] : b;
     f4 z = *reinterpret_cast<const f4 *>(b1 + 4 * lane);
     for (int64_t t = ptr[i]; t < ptr[i + 1]; ++t) {
       const int j = col[t];
-      if (j < 0 || j >= n) continue;
-      const float r = val[t];
-      const uint2 wa = *reinterpret_cast<const uint2 *>(W1T + (int64_t)j * 256 + 4 * lane);
-      const uint2 wm = *reinterpret_cast<const uint2 *>(W1T + (int64_t)(n + j) * 256 + 4 * lane);
-      z[0] += __builtin_fmaf(r, bf2f((uint16_t)(wa.x & 0xffff)), bf2f((uint16_t)(wm.x & 0xffff)));
-      z[1] += __builtin_fmaf(r, bf2f((uint16_t)(wa.x >> 16)), bf2f((uint16_t)(wm.x >> 16)));
-      z[2] += __builtin_fmaf(r, bf2f((uint16_t)(wa.y & 0xffff)), bf2f((uint16_t)(wm.y & 0xffff)));
-      z[3] += __builtin_fmaf(r, bf2f((uint16_t)(wa.y >> 16)), bf2f((uint16_t)(wm.y >> 16)));
+      const bool ok = j >= 0 && j < n;
+      uint32_t p1, p2;
+      value_pairs(val[t], ok, p1, p2);
+      layer1_step(z, w1_pairs(rs, ok ? j : -1, lane), p1, p2);
     }
     if (z1) *reinterpret_cast<f4 *>(z1 + b * 256 + 4 * lane) = z;
     f4 hv;
@@ -101,57 +165,83 @@ __global__ __launch_bounds__(256) void k_layer1(int64_t B, const int64_t *__rest
 // Block tile 64 x 64, four wavefronts of 32 x 32 (v_mfma_f32_32x32x16_bf16), K chunks of 32.
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
 
+// Operand staging of the BF16 MFMA products.  A 64-row tile of X(r, k) = X[r*sr + k*sk] is
+// staged one strip of up to kStripK k values at a time: every thread first issues all of its
+// loads (8 chunks of 32 k, 8 values each, zero outside R x Kd), then packs each group of 8
+// consecutive k into one 16-byte LDS store (bfloat16, round to nearest even, k-fast rows of
+// pitch kLdk).  Threads are laid out so that global reads are contiguous across lanes: four
+// threads per row when k is the fast index, 64 rows per k-group when the row is.
+constexpr int kStripK = 256;
+constexpr int kLdk = kStripK + 8;  // LDS row pitch in bf16 (pads banks)
+
+__device__ __forceinline__ void strip_load(float (&v)[8][8], const float *__restrict__ X, int64_t sr, int64_t sk,
+                                           int64_t r0, int64_t R, int k0, int Kd) {
+  const int t = threadIdx.x;
+  const bool kfast = sk == 1;
+  const int row = kfast ? t >> 2 : t & 63, kg = kfast ? t & 3 : t >> 6;
+  const int64_t gr = r0 + row;
+  const bool rok = gr < R;
+  const float *base = X + (rok ? gr : 0) * sr;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int gk = k0 + 32 * c + 8 * kg + e;
+      v[c][e] = (rok && gk < Kd) ? base[(int64_t)gk * sk] : 0.f;
+    }
+}
+
+__device__ __forceinline__ void strip_store(uint16_t *__restrict__ Xs, const float (&v)[8][8], bool kfast, int nch) {
+  const int t = threadIdx.x;
+  const int row = kfast ? t >> 2 : t & 63, kg = kfast ? t & 3 : t >> 6;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (c < nch) {
+      uint32_t pk[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pk[e] = (uint32_t)f2bf(v[c][2 * e]) | ((uint32_t)f2bf(v[c][2 * e + 1]) << 16);
+      *reinterpret_cast<uint4 *>(Xs + row * kLdk + 32 * c + 8 * kg) = uint4{pk[0], pk[1], pk[2], pk[3]};
+    }
+  }
+}
+
+// acc += As[wm*32 .., 0..klen) x Bs[wn*32 .., 0..klen)^T on v_mfma_f32_32x32x16_bf16; lane (i, g)
+// supplies A[i][ks + 8g .. +8] and B[j][ks + 8g .. +8]
+__device__ __forceinline__ void strip_mfma(f16 &acc, const uint16_t *__restrict__ As, const uint16_t *__restrict__ Bs,
+                                           int wm, int wn, int klen) {
+  const int lane = threadIdx.x & 63, i = lane & 31, g = lane >> 5;
+  const uint16_t *pa = As + (wm * 32 + i) * kLdk + 8 * g, *pb = Bs + (wn * 32 + i) * kLdk + 8 * g;
+  for (int ks = 0; ks < klen; ks += 16) {
+    const uint4 av = *reinterpret_cast<const uint4 *>(pa + ks);
+    const uint4 bv = *reinterpret_cast<const uint4 *>(pb + ks);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                  acc, 0, 0, 0);
+  }
+}
+
+// C[m][n] = epilogue(sum_k A(m, k) B(n, k)), A(m, k) = A[m*sam + k*sak], B(n, k) = B[n*sbn + k*sbk];
+// block tile 64 x 64, four wavefronts of 32 x 32.
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int Kd, const float *__restrict__ A, int64_t sam,
                                               int64_t sak, const float *__restrict__ Bm, int64_t sbn, int64_t sbk,
                                               float *__restrict__ C, int64_t ldc, const float *__restrict__ bias,
                                               float *__restrict__ Z, int64_t ldz) {
-  constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;  // LDS row pitch in bf16 (pads banks)
-  __shared__ uint16_t As[TM * LDK];
-  __shared__ uint16_t Bs[TN * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * kLdk];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
+  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
   f16 acc = {};
-  const bool a_kfast = sak == 1, b_kfast = sbk == 1;
-  for (int k0 = 0; k0 < Kd; k0 += TK) {
-    for (int e = threadIdx.x; e < TM * TK; e += 256) {
-      int mm, kk;
-      if (a_kfast) {
-        mm = e / TK;
-        kk = e % TK;
-      } else {
-        mm = e % TM;
-        kk = e / TM;
-      }
-      const int64_t gm = m0 + mm;
-      const int gk = k0 + kk;
-      As[mm * LDK + kk] = (gm < M && gk < Kd) ? f2bf(A[gm * sam + (int64_t)gk * sak]) : 0;
-    }
-    for (int e = threadIdx.x; e < TN * TK; e += 256) {
-      int nn, kk;
-      if (b_kfast) {
-        nn = e / TK;
-        kk = e % TK;
-      } else {
-        nn = e % TN;
-        kk = e / TN;
-      }
-      const int64_t gn = n0 + nn;
-      const int gk = k0 + kk;
-      Bs[nn * LDK + kk] = (gn < N && gk < Kd) ? f2bf(Bm[gn * sbn + (int64_t)gk * sbk]) : 0;
-    }
+  for (int k0 = 0; k0 < Kd; k0 += kStripK) {
+    const int klen = Kd - k0 < kStripK ? Kd - k0 : kStripK;
+    float va[8][8], vb[8][8];
+    strip_load(va, A, sam, sak, m0, M, k0, Kd);
+    strip_load(vb, Bm, sbn, sbk, n0, N, k0, Kd);
+    if (k0 > 0) __syncthreads();  // the previous strip's LDS reads are done
+    strip_store(As, va, sak == 1, (klen + 31) / 32);
+    strip_store(Bs, vb, sbk == 1, (klen + 31) / 32);
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < TK; ks += 16) {
-      // lane (i, g): A[i][ks + 8g .. +8], B[j][ks + 8g .. +8]
-      const int i = lane & 31, g = lane >> 5;
-      const uint4 av = *reinterpret_cast<const uint4 *>(As + (wm * 32 + i) * LDK + ks + 8 * g);
-      const uint4 bv = *reinterpret_cast<const uint4 *>(Bs + (wn * 32 + i) * LDK + ks + 8 * g);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
-                                                    acc, 0, 0, 0);
-    }
-    __syncthreads();
+    strip_mfma(acc, As, Bs, wm, wn, klen);
   }
   const int jc = lane & 31, hf = lane >> 5;
   const int64_t gn = n0 + wn * 32 + jc;
@@ -167,6 +257,103 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int Kd, const float 
     }
     if (EPI == EPI_GELU_GRAD) x *= gelu_grad(Z[gm * ldz + gn]);
     C[gm * ldc + gn] = x;
+  }
+}
+
+// Weight gradient of a dense layer over a batch, split over the batch: slice s = blockIdx.z
+// of kc batch rows writes
+//   part[s][m][n] = sum_{b in s} A[b][m] Bv[b][n]     (bfloat16 products, float32 accumulation)
+//   part[s][M*N + m] = sum_{b in s} A[b][m]            (the bias gradient, float32)
+// with A = the layer's output gradient (Bsz x M, row-major) and Bv = its input (Bsz x N).  The
+// slices are added in order by k_reduce_slices, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_gemm_wgrad(int M, int N, int Bsz, int kc, const float *__restrict__ A,
+                                                    const float *__restrict__ Bv, float *__restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * kLdk];
+  __shared__ float bred[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int s = blockIdx.z;
+  const int b0 = s * kc, b1 = b0 + kc < Bsz ? b0 + kc : Bsz;
+  const float *Ag = A + (int64_t)b0 * M, *Bg = Bv + (int64_t)b0 * N;
+  const int kd = b1 - b0;
+  float bsum = 0.f;  // thread (row t % 64, k-group t / 64): its staged values of A, in order
+  f16 acc = {};
+  for (int k0 = 0; k0 < kd; k0 += kStripK) {
+    const int klen = kd - k0 < kStripK ? kd - k0 : kStripK;
+    float va[8][8], vb[8][8];
+    strip_load(va, Ag, 1, M, m0, M, k0, kd);
+    strip_load(vb, Bg, 1, N, n0, N, k0, kd);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bsum += va[c][e];
+    if (k0 > 0) __syncthreads();
+    strip_store(As, va, false, (klen + 31) / 32);
+    strip_store(Bs, vb, false, (klen + 31) / 32);
+    __syncthreads();
+    strip_mfma(acc, As, Bs, wm, wn, klen);
+  }
+  float *dst = part + (int64_t)s * ((int64_t)M * N + M);
+  const int jc = lane & 31, hf = lane >> 5;
+  const int64_t gn = n0 + wn * 32 + jc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t gm = m0 + wm * 32 + 8 * (v / 4) + 4 * hf + (v % 4);
+    if (gm < M && gn < N) dst[gm * N + gn] = acc[v];
+  }
+  if (blockIdx.x == 0) {
+    bred[threadIdx.x >> 6][threadIdx.x & 63] = bsum;
+    __syncthreads();
+    if (threadIdx.x < 64 && m0 + threadIdx.x < M)
+      dst[(int64_t)M * N + m0 + threadIdx.x] =
+          ((bred[0][threadIdx.x] + bred[1][threadIdx.x]) + bred[2][threadIdx.x]) + bred[3][threadIdx.x];
+  }
+}
+
+// out[i] = sum_{s = 0..S-1} part[s][i] in slice order (eight slices' loads in flight)
+__global__ __launch_bounds__(256) void k_reduce_slices(int64_t total, int S, const float *__restrict__ part,
+                                                       float *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    float acc = 0.f;
+    int s = 0;
+    for (; s + 8 <= S; s += 8) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = part[(int64_t)(s + e) * total + i];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc += x[e];
+    }
+    for (; s < S; ++s) acc += part[(int64_t)s * total + i];
+    out[i] = acc;
+  }
+}
+
+// Dense input rows of a batch, x_b = [r * mask ; mask] (Bsz x 2n float32), one wavefront per
+// row: the row is assembled in LDS (zeros, then its observed entries), then written out whole.
+// Entries with a column outside [0, n) are left out, as in the sparse first layer.
+__global__ __launch_bounds__(64) void k_dense_x(int64_t Bsz, const int64_t *__restrict__ rows,
+                                                const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                                const float *__restrict__ val, int n, float *__restrict__ X) {
+  extern __shared__ float xs[];
+  const int lane = threadIdx.x;
+  const int twon = 2 * n;
+  for (int64_t b = blockIdx.x; b < Bsz; b += gridDim.x) {
+    for (int c = lane; c < twon; c += 64) xs[c] = 0.f;
+    __syncthreads();
+    const int64_t i = rows ? rows[b] : b;
+    for (int64_t t = ptr[i] + lane; t < ptr[i + 1]; t += 64) {
+      const int j = col[t];
+      if (j >= 0 && j < n) {
+        xs[j] = val[t];
+        xs[n + j] = 1.0f;
+      }
+    }
+    __syncthreads();
+    float *dst = X + b * twon;
+    for (int c = lane; c < twon; c += 64) dst[c] = xs[c];
+    __syncthreads();
   }
 }
 
@@ -204,101 +391,100 @@ __global__ __launch_bounds__(256) void k_loss(int64_t B, int k, const float *__r
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_loss_final(const double *__restrict__ part, int nparts, int64_t total, double *__restrict__ loss_d,
-                             float *__restrict__ loss_f) {
+// Optimizer state on the device, so that a recorded training step can be replayed as is:
+// t = Adam steps taken, cursor = batch index within the epoch, c1/c2 = bias corrections of
+// the next step, 1 - beta1^(t+1) and 1 - beta2^(t+1).
+struct TrainState {
+  int64_t t, cursor;
+  float c1, c2;
+};
+
+__device__ __forceinline__ void train_state_set(TrainState *st, int64_t t) {
+  st->t = t;
+  st->c1 = (float)(1.0 - pow(0.9, (double)(t + 1)));
+  st->c2 = (float)(1.0 - pow(0.999, (double)(t + 1)));
+}
+
+__global__ void k_train_state_reset(TrainState *st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += part[i];
+    train_state_set(st, 0);
+    st->cursor = 0;
+  }
+}
+
+// end of a training step: one more Adam step, next batch
+__global__ void k_step_end(TrainState *st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    train_state_set(st, st->t + 1);
+    st->cursor += 1;
+  }
+}
+
+__global__ void k_loss_final(const double *__restrict__ part, int nparts, int64_t total, double *__restrict__ loss_d,
+                             float *__restrict__ loss_f, const TrainState *__restrict__ st,
+                             float *__restrict__ loss_steps) {
+  // lane l adds partials l, l + 64, ... in order, then a fixed butterfly combines the lanes
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int i = lane; i < nparts; i += 64) s += part[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) {
     s /= (double)total;
     if (loss_d) loss_d[0] = s;
     if (loss_f) loss_f[0] = (float)s;
+    if (loss_steps) loss_steps[st->t] = (float)s;
   }
 }
 
-// out[c] = sum_b D[b][c] for c < N (bias gradients), fixed order
-__global__ void k_colsum(int64_t B, int N, const float *__restrict__ D, float *__restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  float s = 0.f;
-  for (int64_t b = 0; b < B; ++b) s += D[b * N + c];
-  out[c] = s;
+// ---- seeded shuffle of the training rows, on the device
+// SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014): a 64-bit mixing bijection.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
 }
 
-// Batch CSR gather: cnt[b] = |O_rows[b]|, then entries copied behind an exclusive scan.
-__global__ void k_batch_count(int64_t B, const int64_t *__restrict__ rows, const int64_t *__restrict__ ptr,
-                              int64_t *__restrict__ bptr) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < B) {
-    const int64_t i = rows ? rows[b] : b;
-    bptr[b + 1] = ptr[i + 1] - ptr[i];
-  }
-  if (b == 0) bptr[0] = 0;
-}
-
-__global__ __launch_bounds__(1024) void k_inclusive_scan_i64(int64_t *__restrict__ x, int64_t len) {
-  // single block, in place, len <= a few hundred thousand
-  __shared__ int64_t part[1024];
-  const int64_t per = (len + 1023) / 1024;
-  const int64_t b0 = threadIdx.x * per, b1 = b0 + per < len ? b0 + per : len;
-  int64_t acc = 0;
-  for (int64_t i = b0; i < b1; ++i) acc += x[i];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-  for (int64_t i = b0; i < b1; ++i) {
-    run += x[i];
-    x[i] = run;
-  }
-}
-
-__global__ void k_batch_gather(int64_t B, const int64_t *__restrict__ rows, const int64_t *__restrict__ ptr,
-                               const int32_t *__restrict__ col, const float *__restrict__ val,
-                               const int64_t *__restrict__ bptr, int n, int32_t *__restrict__ bcol,
-                               float *__restrict__ bval) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < B; b += nw) {
-    const int64_t i = rows ? rows[b] : b;
-    const int64_t s = ptr[i], c = ptr[i + 1] - s, d = bptr[b];
-    for (int64_t t = lane; t < c; t += 64) {
-      bcol[d + t] = col[s + t];  // out-of-range columns are dropped by the column view
-      bval[d + t] = val[s + t];
-    }
-  }
-}
-
-// Sparse W1 gradient: for input feature j (value part j, mask part n + j),
-//   g[h][j]     = sum_{b: j in O_b} dz1[b][h] r_bj,   g[h][n + j] = sum_{b: j in O_b} dz1[b][h]
-// one wavefront per feature over the batch's column view, lanes own 4 hidden units each.
-__global__ __launch_bounds__(256) void k_grad_w1(int n, const int64_t *__restrict__ cp, const int32_t *__restrict__ rb,
-                                                 const float *__restrict__ rv, const float *__restrict__ dz1,
-                                                 float *__restrict__ g) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (j >= n) return;
-  f4 gr = {0.f, 0.f, 0.f, 0.f}, gm = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t e = cp[j]; e < cp[j + 1]; ++e) {
-    const f4 d = *reinterpret_cast<const f4 *>(dz1 + (int64_t)rb[e] * 256 + 4 * lane);
-    const float r = rv[e];
-    gr += r * d;
-    gm += d;
-  }
-  const int64_t twon = 2 * (int64_t)n;
+// perm[i] for i < m: a four-round balanced Feistel network on 2h-bit integers (4^h >= m,
+// round keys key_r = mix64(mix64(seed) + 4 epoch + r), round function mix64(R ^ key_r) masked to
+// h bits) is a bijection of [0, 4^h); walking its cycle from i until the value falls below m
+// restricts it to a bijection of [0, m) (every cycle through i returns to i, so the walk ends).
+// Thread 0 also rewinds the batch cursor of the epoch.
+__global__ __launch_bounds__(256) void k_shuffle(int64_t m, int h, uint64_t seed, int64_t epoch,
+                                                 int64_t *__restrict__ perm, TrainState *__restrict__ st) {
+  const uint64_t base = mix64(seed) + 4ull * (uint64_t)epoch;
+  uint64_t key[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    g[(int64_t)(4 * lane + q) * twon + j] = gr[q];
-    g[(int64_t)(4 * lane + q) * twon + n + j] = gm[q];
+  for (int r = 0; r < 4; ++r) key[r] = mix64(base + (uint64_t)r);
+  const uint64_t mask = (1ull << h) - 1ull;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+    uint64_t x = (uint64_t)i;
+    do {
+      uint64_t L = x >> h, R = x & mask;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint64_t nl = R;
+        R = L ^ (mix64(R ^ key[r]) & mask);
+        L = nl;
+      }
+      x = (L << h) | R;
+    } while (x >= (uint64_t)m);
+    perm[i] = (int64_t)x;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->cursor = 0;
+}
+
+// the rows of the current batch: rows[t] = perm[cursor * batch + t]
+__global__ __launch_bounds__(256) void k_rows_of_step(const int64_t *__restrict__ perm, int batch,
+                                                      const TrainState *__restrict__ st, int64_t *__restrict__ rows) {
+  const int64_t off = st->cursor * (int64_t)batch;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < batch; t += gridDim.x * 256) rows[t] = perm[off + t];
 }
 
 __global__ void k_adam(int64_t np, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
-                       float *__restrict__ v, float lr, float c1, float c2) {
+                       float *__restrict__ v, float lr, const TrainState *__restrict__ st) {
+  const float c1 = st->c1, c2 = st->c2;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
     const float mi = 0.9f * m[i] + 0.1f * gi;
@@ -331,98 +517,149 @@ __global__ void k_count_u8(int64_t m, const uint8_t *__restrict__ f, int64_t *__
 
 // ---------------------------------------------------------------- fused inference
 // Surrogate fold-in of a tile of kIR rows per block iteration (persistent grid), the network
-// and the fallback test in one kernel: sparse first layer (each wavefront 16 rows, lane l
-// hidden units 4l..4l+3) -> GELU -> bfloat16 tile in LDS -> second layer on BF16 MFMA with
-// this wavefront's 64 columns of W2 held in registers for the whole kernel -> GELU -> LDS
-// (over the first tile) -> third layer on MFMA -> u to global and LDS -> observed-entry RMS
-// residual against the setting factors (four lanes per row) -> fallback flag.  Every
-// arithmetic step matches the batched forward (same products, same order, same roundings).
+// and the fallback test in one kernel:
+//   first layer  each wavefront owns 16 consecutive rows, lane l hidden units 4l..4l+3.  The
+//                row pointers of the 16 rows come in one load, their entries (contiguous in
+//                the CSR) are staged in LDS up to kCap at a time, and the entries are taken as
+//                one stream across the rows: the weight pairs of the next eight entries load
+//                while the current eight are added, and a row is closed (GELU, bfloat16 into
+//                the LDS tile) when the stream passes its end.
+//   second layer BF16 MFMA, this wavefront's 64 output columns, its W2 operands streamed from
+//                the packed copy (L2-resident) four steps ahead -> GELU -> LDS
+//   third layer  MFMA -> u to global and LDS
+//   residual     observed-entry RMS residual against the setting factors (four lanes per row;
+//                the entries from the staging area when they fit) -> fallback flag.
+// Every arithmetic step matches the batched forward (same products, same order, same
+// roundings).
 constexpr int kIR = 64;       // rows per tile
 constexpr int kHP = 256 + 8;  // LDS pitch of an activation row (bf16)
+constexpr int kCap = 176;     // entries staged per wavefront (three blocks per CU up to rank 32)
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 template <int K>
-__global__ __launch_bounds__(256, 2) void k_mlp_infer(int64_t m, const int64_t *__restrict__ ptr,
+__global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col, const float *__restrict__ val,
-                                                      int n, const uint16_t *__restrict__ W1T,
-                                                      const float *__restrict__ b1, const float *__restrict__ W2,
-                                                      const float *__restrict__ b2, const float *__restrict__ W3,
+                                                      int n, const uint32_t *__restrict__ W1P,
+                                                      const float *__restrict__ b1, const uint4 *__restrict__ W2P,
+                                                      const float *__restrict__ b2, const uint4 *__restrict__ W3P,
                                                       const float *__restrict__ b3, const float *__restrict__ F,
                                                       float tau, float *__restrict__ U, float *__restrict__ rho,
                                                       uint8_t *__restrict__ flag) {
   constexpr int CB3 = (K + 31) / 32;  // 32-column blocks of the output layer
+  constexpr int PF = 4;               // W2 steps loaded ahead
   __shared__ __attribute__((aligned(16))) uint16_t Hs[kIR * kHP];
   __shared__ float Us[kIR * K];
+  // per wavefront: {column or -1, value pair 1, value pair 2, value bits} of its rows' entries
+  __shared__ uint4 Stg[4][kCap];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i32 = lane & 31, g = lane >> 5;
-  // B operands of the second layer: W2[64w + 32cb + i32][16ks + 8g .. +8] as bfloat16
-  uint4 w2r[2][16];
-#pragma unroll
-  for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
-      const float *src = W2 + (int64_t)(64 * w + 32 * cb + i32) * 256 + 16 * ks + 8 * g;
-      uint32_t pk[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) pk[e] = (uint32_t)f2bf(src[2 * e]) | ((uint32_t)f2bf(src[2 * e + 1]) << 16);
-      w2r[cb][ks] = uint4{pk[0], pk[1], pk[2], pk[3]};
-    }
   const float b2c[2] = {b2[64 * w + i32], b2[64 * w + 32 + i32]};
+  const f4 b1v = *reinterpret_cast<const f4 *>(b1 + 4 * lane);
+  const uint4 *w2w = W2P + (int64_t)(2 * w) * 16 * 64 + lane;  // step (cb, ks) at w2w[(cb*16 + ks)*64]
+  const __amdgpu_buffer_rsrc_t rs1 = make_rsrc(W1P, (uint64_t)n * 1024);
+  uint4 *stg = Stg[w];
   const int64_t ntiles = (m + kIR - 1) / kIR;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * kIR;
-    // ---- first layer (sparse), GELU, bfloat16 into LDS.  A row's entries are fetched 64 at
-    // a time, one per lane, then taken in order, eight weight gathers in flight at once.
-    for (int q = 0; q < 16; ++q) {
-      const int lr = 16 * w + q;
-      const int64_t row = r0 + lr;
-      f4 z = *reinterpret_cast<const f4 *>(b1 + 4 * lane);
-      const int64_t t0 = row < m ? ptr[row] : 0, t1 = row < m ? ptr[row + 1] : 0;
-      for (int64_t base = t0; base < t1; base += 64) {
-        const int nb = (int)(t1 - base < 64 ? t1 - base : 64);
-        const int jl = lane < nb ? col[base + lane] : -1;
-        const float rl = lane < nb ? val[base + lane] : 0.f;
-        for (int u0 = 0; u0 < nb; u0 += 8) {
-          uint2 wa[8], wm[8];
-          int jj[8];
-          float rr[8];
+    const int64_t rw0 = r0 + 16 * w;
+    // ---- first layer (sparse), GELU, bfloat16 into LDS
+    // lane q <= 16 holds P_q, the first entry of row rw0 + q (rows past m are empty)
+    const int64_t prow = rw0 + (lane < 16 ? lane : 16);
+    const int64_t pv = ptr[prow < m ? prow : m];
+    const int64_t E0 = readlane_i64(pv, 0);
+    const int nent = (int)(readlane_i64(pv, 16) - E0);  // the wavefront's entries, < 2^31
+    int cur = 0;                                      // row of the wavefront being accumulated
+    int nxt = (int)(readlane_i64(pv, 1) - E0);        // first entry (relative) after it
+    f4 z = b1v;
+    auto close_row = [&]() {
+      const uint32_t lo = (uint32_t)f2bf(gelu(z[0])) | ((uint32_t)f2bf(gelu(z[1])) << 16);
+      const uint32_t hi = (uint32_t)f2bf(gelu(z[2])) | ((uint32_t)f2bf(gelu(z[3])) << 16);
+      *reinterpret_cast<uint2 *>(Hs + (16 * w + cur) * kHP + 4 * lane) = uint2{lo, hi};
+      ++cur;
+      z = b1v;
+      nxt = cur < 16 ? (int)(readlane_i64(pv, cur + 1) - E0) : INT_MAX;
+    };
+    for (int cs = 0; cs < nent; cs += kCap) {
+      const int clen = nent - cs < kCap ? nent - cs : kCap;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();  // the previous chunk's reads of the staging area are done
+      for (int t = lane; t < clen; t += 64) {
+        const int j = col[E0 + cs + t];
+        const float r = val[E0 + cs + t];
+        const bool ok = j >= 0 && j < n;
+        uint32_t p1, p2;
+        value_pairs(r, ok, p1, p2);
+        stg[t] = uint4{(uint32_t)(ok ? j : -1), p1, p2, __builtin_bit_cast(uint32_t, r)};
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint4 wv[8];
+      uint32_t q1[8], q2[8];
+      auto fetch = [&](int u0) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int t = u0 + e < nb ? u0 + e : nb - 1;
-            jj[e] = __builtin_amdgcn_readlane(jl, t);
-            rr[e] = readlane_f32(rl, t);
-            const int js = (jj[e] >= 0 && jj[e] < n) ? jj[e] : 0;
-            wa[e] = *reinterpret_cast<const uint2 *>(W1T + (int64_t)js * 256 + 4 * lane);
-            wm[e] = *reinterpret_cast<const uint2 *>(W1T + (int64_t)(n + js) * 256 + 4 * lane);
-          }
+        for (int e = 0; e < 8; ++e) {
+          const uint4 st = stg[u0 + e < clen ? u0 + e : clen - 1];
+          q1[e] = u0 + e < clen ? st.y : 0u;  // past the chunk: adds nothing, and is not taken
+          q2[e] = u0 + e < clen ? st.z : 0u;
+          wv[e] = w1_pairs(rs1, (int)st.x, lane);
+        }
+      };
+      fetch(0);
+      for (int u0 = 0; u0 < clen; u0 += 8) {
+        uint4 cw[8];
+        uint32_t c1[8], c2[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            if (u0 + e < nb && jj[e] >= 0 && jj[e] < n) {  // wave-uniform
-              const float r = rr[e];
-              z[0] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].x & 0xffff)), bf2f((uint16_t)(wm[e].x & 0xffff)));
-              z[1] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].x >> 16)), bf2f((uint16_t)(wm[e].x >> 16)));
-              z[2] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].y & 0xffff)), bf2f((uint16_t)(wm[e].y & 0xffff)));
-              z[3] += __builtin_fmaf(r, bf2f((uint16_t)(wa[e].y >> 16)), bf2f((uint16_t)(wm[e].y >> 16)));
-            }
+        for (int e = 0; e < 8; ++e) {
+          cw[e] = wv[e];
+          c1[e] = q1[e];
+          c2[e] = q2[e];
+        }
+        if (u0 + 8 < clen) fetch(u0 + 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (u0 + e < clen) {
+            while (cs + u0 + e >= nxt) close_row();
+            layer1_step(z, cw[e], c1[e], c2[e]);
           }
         }
       }
-      const uint32_t lo = (uint32_t)f2bf(gelu(z[0])) | ((uint32_t)f2bf(gelu(z[1])) << 16);
-      const uint32_t hi = (uint32_t)f2bf(gelu(z[2])) | ((uint32_t)f2bf(gelu(z[3])) << 16);
-      *reinterpret_cast<uint2 *>(Hs + lr * kHP + 4 * lane) = uint2{lo, hi};
     }
+    while (cur < 16) close_row();
     __syncthreads();
     // ---- second layer: this wavefront's 64 output columns for all kIR rows
     f16 acc[2][2] = {};
+    {
+      // an offset the compiler cannot see through, so that the W2 loads stay in the tile loop
+      // instead of being hoisted into 128 live registers
+      int opq = 0;
+      asm volatile("" : "+v"(opq));
+      const uint4 *w2t = w2w + opq;
+      uint4 ring[PF][2];
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
+      for (int ks = 0; ks < PF; ++ks)
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32) * kHP + 16 * ks + 8 * g);
+        for (int cb = 0; cb < 2; ++cb) ring[ks][cb] = w2t[(cb * 16 + ks) * 64];
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                               __builtin_bit_cast(bf16x8, w2r[cb][ks]), acc[rb][cb],
-                                                               0, 0, 0);
+      for (int ks = 0; ks < 16; ++ks) {
+        const uint4 bw0 = ring[ks % PF][0], bw1 = ring[ks % PF][1];
+        if (ks + PF < 16) {
+          ring[ks % PF][0] = w2t[(ks + PF) * 64];
+          ring[ks % PF][1] = w2t[(16 + ks + PF) * 64];
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32) * kHP + 16 * ks + 8 * g);
+          acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                              __builtin_bit_cast(bf16x8, bw0), acc[rb][0], 0, 0, 0);
+          acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                              __builtin_bit_cast(bf16x8, bw1), acc[rb][1], 0, 0, 0);
+        }
       }
     }
     __syncthreads();  // every wavefront has read the first layer's tile
@@ -441,17 +678,16 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(int64_t m, const int64_t *
       const int rb = w & 1, cb = w >> 1;
       const int oc = 32 * cb + i32;  // output column supplied / received by this lane
       f16 acc3 = {};
+      int opq = 0;
+      asm volatile("" : "+v"(opq));  // keeps the operand loads in the tile loop
+      const uint4 *w3t = W3P + cb * 16 * 64 + lane + opq;
+      uint4 bw[16];
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) bw[ks] = w3t[ks * 64];
 #pragma unroll
       for (int ks = 0; ks < 16; ++ks) {
         const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32) * kHP + 16 * ks + 8 * g);
-        uint32_t pk[4] = {0, 0, 0, 0};
-        if (oc < K) {
-          const float *src = W3 + (int64_t)oc * 256 + 16 * ks + 8 * g;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) pk[e] = (uint32_t)f2bf(src[2 * e]) | ((uint32_t)f2bf(src[2 * e + 1]) << 16);
-        }
-        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                      __builtin_bit_cast(bf16x8, uint4{pk[0], pk[1], pk[2], pk[3]}),
+        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bw[ks]),
                                                       acc3, 0, 0, 0);
       }
       if (oc < K) {
@@ -471,11 +707,12 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(int64_t m, const int64_t *
       constexpr int KQ = K / 4;
       const int lr = 16 * w + (lane >> 2), pq = lane & 3;
       const int64_t row = r0 + lr;
-      int64_t t0 = 0, t1 = 0;
-      if (row < m) {
-        t0 = ptr[row];
-        t1 = ptr[row + 1];
-      }
+      // the row's entries [P_q, P_q+1) from the lanes that loaded them (empty past m)
+      const int q = lane >> 2;
+      const int64_t t0 = (int64_t)(((uint64_t)(uint32_t)__shfl((int)((uint64_t)pv >> 32), q, 64) << 32) |
+                                   (uint32_t)__shfl((int)(uint32_t)pv, q, 64));
+      const int64_t t1 = (int64_t)(((uint64_t)(uint32_t)__shfl((int)((uint64_t)pv >> 32), q + 1, 64) << 32) |
+                                   (uint32_t)__shfl((int)(uint32_t)pv, q + 1, 64));
       const int cnt = (int)(t1 - t0);
       int cmax = cnt;
 #pragma unroll
@@ -484,6 +721,8 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(int64_t m, const int64_t *
         cmax = o > cmax ? o : cmax;
       }
       float ssq = 0.f;
+      const bool staged = nent <= kCap;  // wave-uniform: this row's entries are in stg
+      const int sofs = (int)(t0 - E0);
       for (int t0b = 0; t0b < cmax; t0b += 4) {
         // four entries in flight: indices and values, then the factor rows, then the dots
         int jv[4];
@@ -493,10 +732,16 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(int64_t m, const int64_t *
         for (int e = 0; e < 4; ++e) {
           const int t = t0b + e;
           const bool in = t < cnt;
-          jv[e] = in ? col[t0 + t] : -1;
-          rv[e] = in ? val[t0 + t] : 0.f;
-          const bool ok = jv[e] >= 0 && jv[e] < n;
-          fv[e] = F + (int64_t)(ok ? jv[e] : 0) * K + pq * KQ;
+          if (staged) {
+            const uint4 st = stg[in ? sofs + t : 0];
+            jv[e] = in ? (int)st.x : -1;
+            rv[e] = in ? __builtin_bit_cast(float, st.w) : 0.f;
+          } else {
+            jv[e] = in ? col[t0 + t] : -1;
+            rv[e] = in ? val[t0 + t] : 0.f;
+          }
+          const bool okj = jv[e] >= 0 && jv[e] < n;
+          fv[e] = F + (int64_t)(okj ? jv[e] : 0) * K + pq * KQ;
         }
         float fx[4][KQ];
 #pragma unroll
@@ -533,19 +778,16 @@ struct open_mlp {
   int64_t np = 0;
   int64_t off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
   float *w = nullptr, *g = nullptr, *am = nullptr, *av = nullptr;  // masters, gradient, Adam moments
-  uint16_t *w1t = nullptr;                                         // bf16 W1 transposed (2n x H)
-  int64_t step = 0;
+  uint32_t *w1p = nullptr;                                         // W1 weight pairs, bfloat16 (n x H)
+  uint4 *w2p = nullptr;                                            // W2 as inference MFMA operands
+  uint4 *w3p = nullptr;                                            // W3 as inference MFMA operands
+  openk::TrainState *tstate = nullptr;                             // device optimizer state
   // activations for a batch of up to cap rows
   int64_t cap = 0;
   float *z1 = nullptr, *h1 = nullptr, *z2 = nullptr, *h2 = nullptr, *out = nullptr, *dout = nullptr;
   float *d2 = nullptr, *d1 = nullptr;
-  int64_t *bptr = nullptr;
-  int32_t *bcol = nullptr;
-  float *bval = nullptr;
-  int64_t bnnz_cap = 0;
-  int64_t *ccp = nullptr;
-  int32_t *crb = nullptr;
-  float *crv = nullptr;
+  float *xd = nullptr;     // dense input rows of the batch (batch x 2n), for the W1 gradient
+  float *wpart = nullptr;  // split-over-the-batch partials of the weight and bias gradients
   double *part = nullptr, *loss = nullptr;
   // inference scratch
   int64_t icap = 0;
@@ -559,66 +801,56 @@ namespace openk {
 constexpr int kMaxBatchRows = 16384;
 constexpr int kLossBlocks = 256;
 
-static void mlp_free_batch(open_mlp *p) {
-  float *fs[] = {p->z1, p->h1, p->z2, p->h2, p->out, p->dout, p->d2, p->d1, p->bval, p->crv};
-  for (float *f : fs) (void)hipFree(f);
-  (void)hipFree(p->bptr);
-  (void)hipFree(p->bcol);
-  (void)hipFree(p->ccp);
-  (void)hipFree(p->crb);
-  p->z1 = p->h1 = p->z2 = p->h2 = p->out = p->dout = p->d2 = p->d1 = p->bval = p->crv = nullptr;
-  p->bptr = p->ccp = nullptr;
-  p->bcol = p->crb = nullptr;
-  p->cap = 0;
-  p->bnnz_cap = 0;
+// batch slices of the weight-gradient product of an M x N layer: about 1024 blocks over the
+// 64 x 64 output tiles, each slice a multiple of 32 batch rows
+static int wgrad_slices(int64_t B, int M, int N, int *kc) {
+  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  int64_t S = (1024 + tiles - 1) / tiles;
+  if (S > 256) S = 256;
+  int64_t c = (B + S - 1) / S;
+  c = (c + 31) / 32 * 32;
+  *kc = (int)c;
+  return (int)((B + c - 1) / c);
 }
 
-static open_status mlp_batch_buffers(open_mlp *p, int64_t B, int64_t bnnz) {
+static int64_t wgrad_part_floats(int64_t B, int M, int N) {
+  int kc;
+  return (int64_t)wgrad_slices(B, M, N, &kc) * ((int64_t)M * N + M);
+}
+
+static void mlp_free_batch(open_mlp *p) {
+  float *fs[] = {p->z1, p->h1, p->z2, p->h2, p->out, p->dout, p->d2, p->d1, p->xd, p->wpart};
+  for (float *f : fs) (void)hipFree(f);
+  p->z1 = p->h1 = p->z2 = p->h2 = p->out = p->dout = p->d2 = p->d1 = p->xd = p->wpart = nullptr;
+  p->cap = 0;
+}
+
+static open_status mlp_batch_buffers(open_mlp *p, int64_t B) {
   open_ctx *ctx = p->ctx;
-  if (B > p->cap) {
-    OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    float *keep_bval = p->bval, *keep_crv = p->crv;
-    int32_t *keep_bcol = p->bcol, *keep_crb = p->crb;
-    int64_t keep_bnnz = p->bnnz_cap;
-    p->bval = p->crv = nullptr;
-    p->bcol = p->crb = nullptr;
+  if (B <= p->cap) return OPEN_OK;
+  if (ctx->capturing) return fail(ctx, OPEN_E_UNSUPPORTED, "buffer growth during graph capture");
+  OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  mlp_free_batch(p);
+  const size_t a = sizeof(float) * (size_t)B * p->H, o = sizeof(float) * (size_t)B * p->k;
+  const size_t x = sizeof(float) * (size_t)B * 2 * p->n;
+  int64_t wp = wgrad_part_floats(B, p->k, p->H);
+  if (wgrad_part_floats(B, p->H, p->H) > wp) wp = wgrad_part_floats(B, p->H, p->H);
+  if (wgrad_part_floats(B, p->H, 2 * p->n) > wp) wp = wgrad_part_floats(B, p->H, 2 * p->n);
+  if (hipMalloc(&p->z1, a) || hipMalloc(&p->h1, a) || hipMalloc(&p->z2, a) || hipMalloc(&p->h2, a) ||
+      hipMalloc(&p->out, o) || hipMalloc(&p->dout, o) || hipMalloc(&p->d2, a) || hipMalloc(&p->d1, a) ||
+      hipMalloc(&p->xd, x) || hipMalloc(&p->wpart, sizeof(float) * (size_t)wp)) {
+    (void)hipGetLastError();
     mlp_free_batch(p);
-    p->bval = keep_bval;
-    p->crv = keep_crv;
-    p->bcol = keep_bcol;
-    p->crb = keep_crb;
-    p->bnnz_cap = keep_bnnz;
-    const size_t a = sizeof(float) * (size_t)B * p->H, o = sizeof(float) * (size_t)B * p->k;
-    if (hipMalloc(&p->z1, a) || hipMalloc(&p->h1, a) || hipMalloc(&p->z2, a) || hipMalloc(&p->h2, a) ||
-        hipMalloc(&p->out, o) || hipMalloc(&p->dout, o) || hipMalloc(&p->d2, a) || hipMalloc(&p->d1, a) ||
-        hipMalloc(&p->bptr, sizeof(int64_t) * (B + 1)) || hipMalloc(&p->ccp, sizeof(int64_t) * (p->n + 1))) {
-      (void)hipGetLastError();
-      mlp_free_batch(p);
-      return fail(ctx, OPEN_E_NOMEM, "surrogate batch buffers");
-    }
-    p->cap = B;
+    return fail(ctx, OPEN_E_NOMEM, "surrogate batch buffers");
   }
-  if (bnnz > p->bnnz_cap) {
-    OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    (void)hipFree(p->bcol);
-    (void)hipFree(p->bval);
-    (void)hipFree(p->crb);
-    (void)hipFree(p->crv);
-    p->bcol = p->crb = nullptr;
-    p->bval = p->crv = nullptr;
-    const int64_t want = bnnz + bnnz / 4 + 64;
-    if (hipMalloc(&p->bcol, sizeof(int32_t) * want) || hipMalloc(&p->bval, sizeof(float) * want) ||
-        hipMalloc(&p->crb, sizeof(int32_t) * want) || hipMalloc(&p->crv, sizeof(float) * want)) {
-      (void)hipGetLastError();
-      return fail(ctx, OPEN_E_NOMEM, "surrogate batch buffers");
-    }
-    p->bnnz_cap = want;
-  }
+  p->cap = B;
   return OPEN_OK;
 }
 
 static open_status mlp_repack(open_mlp *p) {
-  OPEN_LAUNCH(p->ctx, "mlp_pack_w1t", k_pack_w1t, dim3(1024), dim3(256), 0, p->w, p->H, 2 * p->n, p->w1t);
+  OPEN_LAUNCH(p->ctx, "mlp_pack_w1p", k_pack_w1p, dim3(1024), dim3(256), 0, p->w, p->H, p->n, p->w1p);
+  OPEN_LAUNCH(p->ctx, "mlp_pack_w2p", k_pack_w2p, dim3(32), dim3(256), 0, p->w + p->off_w2, p->w2p);
+  OPEN_LAUNCH(p->ctx, "mlp_pack_w3p", k_pack_w3p, dim3(8), dim3(256), 0, p->w + p->off_w3, p->k, p->w3p);
   return OPEN_OK;
 }
 
@@ -629,7 +861,7 @@ static open_status mlp_forward_batch(open_mlp *p, int64_t B, const int64_t *rows
   const int H = p->H, k = p->k;
   int64_t blocks = (B + 3) / 4;
   if (blocks > ctx->num_cu * 8) blocks = ctx->num_cu * 8;
-  OPEN_LAUNCH(ctx, "mlp_layer1", k_layer1, dim3((unsigned)blocks), dim3(256), 0, B, rows, ptr, col, val, p->n, p->w1t,
+  OPEN_LAUNCH(ctx, "mlp_layer1", k_layer1, dim3((unsigned)blocks), dim3(256), 0, B, rows, ptr, col, val, p->n, p->w1p,
               p->w + p->off_b1, p->z1, p->h1);
   open_status st;
   if ((st = gemm<EPI_BIAS_GELU>(ctx, "mlp_gemm_l2", (int)B, H, H, p->h1, H, 1, p->w + p->off_w2, H, 1, p->h2, H,
@@ -639,57 +871,85 @@ static open_status mlp_forward_batch(open_mlp *p, int64_t B, const int64_t *rows
                         p->w + p->off_b3);
 }
 
-// loss + gradient of the batch into p->g (and the loss scalar into loss_d / loss_f)
+// weight and bias gradient of a dense layer (M outputs, N inputs) into g_w (M*N weights
+// followed by M biases), split over the batch and reduced in slice order
+static open_status wgrad(open_mlp *p, const char *name, int M, int N, int64_t B, const float *dY, const float *X,
+                         float *g_w) {
+  open_ctx *ctx = p->ctx;
+  int kc;
+  const int S = wgrad_slices(B, M, N, &kc);
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)S);
+  OPEN_LAUNCH(ctx, name, k_gemm_wgrad, grid, dim3(256), 0, M, N, (int)B, kc, dY, X, p->wpart);
+  const int64_t tot = (int64_t)M * N + M;
+  int64_t blocks = (tot + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  OPEN_LAUNCH(ctx, "mlp_reduce_slices", k_reduce_slices, dim3((unsigned)blocks), dim3(256), 0, tot, S, p->wpart, g_w);
+  return OPEN_OK;
+}
+
+// loss + gradient of the batch into p->g (and the loss scalar into loss_d / loss_f / the
+// per-step record)
 static open_status mlp_backward_batch(open_mlp *p, int64_t B, const int64_t *rows, const int64_t *ptr,
                                       const int32_t *col, const float *val, const float *target, double *loss_d,
-                                      float *loss_f, int64_t bnnz_host) {
+                                      float *loss_f, float *loss_steps) {
   open_ctx *ctx = p->ctx;
   const int H = p->H, k = p->k, n = p->n;
   open_status st;
   OPEN_LAUNCH(ctx, "mlp_loss", k_loss, dim3(kLossBlocks), dim3(256), 0, B, k, p->out, rows, target, p->dout, p->part);
-  OPEN_LAUNCH(ctx, "mlp_loss_final", k_loss_final, dim3(1), dim3(64), 0, p->part, kLossBlocks, B * k, loss_d, loss_f);
+  OPEN_LAUNCH(ctx, "mlp_loss_final", k_loss_final, dim3(1), dim3(64), 0, p->part, kLossBlocks, B * k, loss_d, loss_f,
+              p->tstate, loss_steps);
   float *g = p->g;
-  // layer 3: gW3[o][i] = sum_b dout[b][o] h2[b][i]; gb3 = sum_b dout
-  if ((st = gemm<EPI_STORE>(ctx, "mlp_gemm_gw3", k, H, (int)B, p->dout, 1, k, p->h2, 1, H, g + p->off_w3, H))) return st;
-  OPEN_LAUNCH(ctx, "mlp_colsum", k_colsum, dim3((k + 255) / 256), dim3(256), 0, B, k, p->dout, g + p->off_b3);
+  // layer 3: gW3[o][i] = sum_b dout[b][o] h2[b][i], gb3 = sum_b dout[b]
+  if ((st = wgrad(p, "mlp_wgrad_l3", k, H, B, p->dout, p->h2, g + p->off_w3))) return st;
   // d2 = (dout W3) * GELU'(z2)
   if ((st = gemm<EPI_GELU_GRAD>(ctx, "mlp_gemm_dh2", (int)B, H, k, p->dout, k, 1, p->w + p->off_w3, 1, H, p->d2, H,
                                 nullptr, p->z2, H)))
     return st;
-  // layer 2: gW2[o][i] = sum_b d2[b][o] h1[b][i]; gb2
-  if ((st = gemm<EPI_STORE>(ctx, "mlp_gemm_gw2", H, H, (int)B, p->d2, 1, H, p->h1, 1, H, g + p->off_w2, H))) return st;
-  OPEN_LAUNCH(ctx, "mlp_colsum", k_colsum, dim3((H + 255) / 256), dim3(256), 0, B, H, p->d2, g + p->off_b2);
+  // layer 2: gW2[o][i] = sum_b d2[b][o] h1[b][i], gb2 = sum_b d2[b]
+  if ((st = wgrad(p, "mlp_wgrad_l2", H, H, B, p->d2, p->h1, g + p->off_w2))) return st;
   // d1 = (d2 W2) * GELU'(z1)
   if ((st = gemm<EPI_GELU_GRAD>(ctx, "mlp_gemm_dh1", (int)B, H, H, p->d2, H, 1, p->w + p->off_w2, 1, H, p->d1, H,
                                 nullptr, p->z1, H)))
     return st;
-  OPEN_LAUNCH(ctx, "mlp_colsum", k_colsum, dim3((H + 255) / 256), dim3(256), 0, B, H, p->d1, g + p->off_b1);
-  // sparse layer 1 over the batch's column view
-  OPEN_LAUNCH(ctx, "mlp_batch_count", k_batch_count, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, B, rows, ptr,
-              p->bptr);
-  OPEN_LAUNCH(ctx, "mlp_batch_scan", k_inclusive_scan_i64, dim3(1), dim3(1024), 0, p->bptr + 1, B);
-  OPEN_LAUNCH(ctx, "mlp_batch_gather", k_batch_gather, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, B, rows, ptr, col,
-              val, p->bptr, n, p->bcol, p->bval);
-  (void)bnnz_host;
-  if ((st = csr_to_csc_dev(ctx, B, n, p->bptr, p->bcol, p->bval, p->ccp, p->crb, p->crv))) return st;
-  OPEN_LAUNCH(ctx, "mlp_grad_w1", k_grad_w1, dim3((n + 3) / 4), dim3(256), 0, n, p->ccp, p->crb, p->crv, p->d1, g);
-  return OPEN_OK;
+  // layer 1: gW1[o][c] = sum_b d1[b][o] x_b[c] over the dense input rows, gb1 = sum_b d1[b]
+  // (W1 and b1 are adjacent in the packing)
+  int64_t xb = B < (int64_t)ctx->num_cu * 8 ? B : (int64_t)ctx->num_cu * 8;
+  OPEN_LAUNCH(ctx, "mlp_dense_x", k_dense_x, dim3((unsigned)xb), dim3(64), sizeof(float) * 2 * n, B, rows, ptr, col,
+              val, n, p->xd);
+  return wgrad(p, "mlp_wgrad_l1", H, 2 * n, B, p->d1, p->xd, g);
 }
 
-static open_status batch_nnz(open_mlp *p, int64_t B, const int64_t *rows, const int64_t *ptr, int64_t *out) {
-  // total observed entries of the batch rows, on the host (sizes the gather buffers)
+// one Adam step on a batch (rows nullable: the first B rows), then the step counter
+static open_status mlp_step(open_mlp *p, int64_t B, const int64_t *rows, const int64_t *ptr, const int32_t *col,
+                            const float *val, const float *target, float lr, float *loss_out, float *loss_steps) {
   open_ctx *ctx = p->ctx;
   open_status st;
-  if ((st = mlp_batch_buffers(p, B, 0))) return st;
-  OPEN_LAUNCH(ctx, "mlp_batch_count", k_batch_count, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, B, rows, ptr,
-              p->bptr);
-  OPEN_LAUNCH(ctx, "mlp_batch_scan", k_inclusive_scan_i64, dim3(1), dim3(1024), 0, p->bptr + 1, B);
-  int64_t *h;
-  if ((st = pinned_get(ctx, 64, (void **)&h))) return st;
-  OPEN_HIP_TRY(ctx, hipMemcpyAsync(h, p->bptr + B, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
-  OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  *out = h[0];
-  return OPEN_OK;
+  if ((st = mlp_forward_batch(p, B, rows, ptr, col, val, p->out))) return st;
+  if ((st = mlp_backward_batch(p, B, rows, ptr, col, val, target, p->loss, loss_out, loss_steps))) return st;
+  OPEN_LAUNCH(ctx, "mlp_adam", k_adam, dim3(1024), dim3(256), 0, p->np, p->w, p->g, p->am, p->av, lr, p->tstate);
+  OPEN_LAUNCH(ctx, "mlp_step_end", k_step_end, dim3(1), dim3(64), 0, p->tstate);
+  return mlp_repack(p);
+}
+
+// Seeded initial weights: every weight and bias of a layer with fan-in f uniform on
+// [-1/sqrt(f), 1/sqrt(f)), element e of the flat parameter vector drawn as
+// (mix64(seed ^ mix64(e)) >> 40) * 2^-24 in [0, 1).
+static void seeded_init(open_mlp *p, uint64_t seed, float *w) {
+  struct Seg {
+    int64_t off, len;
+    int fan_in;
+  };
+  const int64_t H = p->H, n2 = 2 * (int64_t)p->n, k = p->k;
+  const Seg seg[] = {{0, H * n2, (int)n2},          {p->off_b1, H, (int)n2}, {p->off_w2, H * H, (int)H},
+                     {p->off_b2, H, (int)H},       {p->off_w3, k * H, (int)H}, {p->off_b3, k, (int)H}};
+  for (const Seg &sg : seg) {
+    const double a = 1.0 / sqrt((double)sg.fan_in);
+    for (int64_t i = 0; i < sg.len; ++i) {
+      const uint64_t e = (uint64_t)(sg.off + i);
+      const double u = (double)(mix64(seed ^ mix64(e)) >> 40) * (1.0 / 16777216.0);
+      w[sg.off + i] = (float)(a * (2.0 * u - 1.0));
+    }
+  }
 }
 
 }  // namespace openk
@@ -703,14 +963,13 @@ int64_t open_mlp_num_params(int32_t n, int32_t k, int32_t hidden) {
 }
 
 open_status open_mlp_create(open_ctx *ctx, open_mlp **out, int32_t n, int32_t k, int32_t hidden,
-                            const float *init_host) {
+                            const float *init_host, uint64_t seed) {
   if (!ctx) return OPEN_E_INVALID;
   if (!out) return fail(ctx, OPEN_E_INVALID, "null output handle");
   *out = nullptr;
   if (hidden != 256) return fail(ctx, OPEN_E_UNSUPPORTED, "hidden width must be 256");
   if (!(k == 8 || k == 16 || k == 32 || k == 64)) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
   if (n <= 0 || n > 4096) return fail(ctx, OPEN_E_INVALID, "n must be in [1, 4096]");
-  if (!init_host) return fail(ctx, OPEN_E_INVALID, "initial weights are required");
   OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
   open_mlp *p = new (std::nothrow) open_mlp();
   if (!p) return fail(ctx, OPEN_E_NOMEM, "handle");
@@ -726,13 +985,27 @@ open_status open_mlp_create(open_ctx *ctx, open_mlp **out, int32_t n, int32_t k,
   p->off_b3 = p->off_w3 + (int64_t)k * hidden;
   const size_t bytes = sizeof(float) * (size_t)p->np;
   if (hipMalloc(&p->w, bytes) || hipMalloc(&p->g, bytes) || hipMalloc(&p->am, bytes) || hipMalloc(&p->av, bytes) ||
-      hipMalloc(&p->w1t, sizeof(uint16_t) * (size_t)hidden * 2 * n) ||
-      hipMalloc(&p->part, sizeof(double) * (kLossBlocks + 8)) || hipMalloc(&p->loss, sizeof(double) * 8)) {
+      hipMalloc(&p->w1p, sizeof(uint32_t) * (size_t)hidden * n) || hipMalloc(&p->w2p, sizeof(uint4) * 8192) ||
+      hipMalloc(&p->w3p, sizeof(uint4) * 2048) ||
+      hipMalloc(&p->part, sizeof(double) * (kLossBlocks + 8)) || hipMalloc(&p->loss, sizeof(double) * 8) ||
+      hipMalloc(&p->tstate, sizeof(TrainState))) {
     (void)hipGetLastError();
     open_mlp_destroy(p);
     return fail(ctx, OPEN_E_NOMEM, "surrogate parameters");
   }
-  open_status st = open_mlp_set_weights(p, init_host);
+  open_status st;
+  if (init_host) {
+    st = open_mlp_set_weights(p, init_host);
+  } else {
+    float *w0 = new (std::nothrow) float[(size_t)p->np];
+    if (!w0) {
+      open_mlp_destroy(p);
+      return fail(ctx, OPEN_E_NOMEM, "initial weights");
+    }
+    seeded_init(p, seed, w0);
+    st = open_mlp_set_weights(p, w0);
+    delete[] w0;
+  }
   if (st) {
     open_mlp_destroy(p);
     return st;
@@ -749,7 +1022,10 @@ open_status open_mlp_destroy(open_mlp *p) {
   (void)hipFree(p->g);
   (void)hipFree(p->am);
   (void)hipFree(p->av);
-  (void)hipFree(p->w1t);
+  (void)hipFree(p->w1p);
+  (void)hipFree(p->w2p);
+  (void)hipFree(p->w3p);
+  (void)hipFree(p->tstate);
   (void)hipFree(p->part);
   (void)hipFree(p->loss);
   (void)hipFree(p->rho);
@@ -773,7 +1049,7 @@ open_status open_mlp_set_weights(open_mlp *p, const float *host_in) {
   OPEN_HIP_TRY(ctx, hipMemcpyAsync(p->w, host_in, sizeof(float) * p->np, hipMemcpyHostToDevice, ctx->stream));
   OPEN_LAUNCH(ctx, "fill", k_fill_i32, dim3(256), dim3(256), 0, (int *)p->am, p->np, 0);
   OPEN_LAUNCH(ctx, "fill", k_fill_i32, dim3(256), dim3(256), 0, (int *)p->av, p->np, 0);
-  p->step = 0;
+  OPEN_LAUNCH(ctx, "mlp_train_state_reset", k_train_state_reset, dim3(1), dim3(64), 0, p->tstate);
   open_status st = mlp_repack(p);
   if (st) return st;
   OPEN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -790,7 +1066,7 @@ open_status open_mlp_forward(open_mlp *p, int64_t m, const int64_t *row_ptr, con
   open_status st;
   for (int64_t b0 = 0; b0 < m; b0 += kMaxBatchRows) {
     const int64_t B = m - b0 < kMaxBatchRows ? m - b0 : kMaxBatchRows;
-    if ((st = mlp_batch_buffers(p, B, 0))) return st;
+    if ((st = mlp_batch_buffers(p, B))) return st;
     if ((st = mlp_forward_batch(p, B, nullptr, row_ptr + b0, col, val, U_hat + b0 * p->k))) return st;
   }
   return OPEN_OK;
@@ -804,11 +1080,9 @@ open_status open_mlp_loss_grad(open_mlp *p, int64_t m, const int64_t *row_ptr, c
     return fail(ctx, OPEN_E_INVALID, "bad shape or pointer (batch of 1..16384 rows)");
   OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
   open_status st;
-  int64_t bnnz;
-  if ((st = batch_nnz(p, m, nullptr, row_ptr, &bnnz))) return st;
-  if ((st = mlp_batch_buffers(p, m, bnnz))) return st;
+  if ((st = mlp_batch_buffers(p, m))) return st;
   if ((st = mlp_forward_batch(p, m, nullptr, row_ptr, col, val, p->out))) return st;
-  if ((st = mlp_backward_batch(p, m, nullptr, row_ptr, col, val, target, p->loss, nullptr, bnnz))) return st;
+  if ((st = mlp_backward_batch(p, m, nullptr, row_ptr, col, val, target, p->loss, nullptr, nullptr))) return st;
   OPEN_HIP_TRY(ctx, hipMemcpyAsync(grads_host, p->g, sizeof(float) * p->np, hipMemcpyDeviceToHost, ctx->stream));
   double *h;
   if ((st = pinned_get(ctx, 64, (void **)&h))) return st;
@@ -829,14 +1103,108 @@ open_status open_mlp_train_step(open_mlp *p, int64_t m, const int64_t *row_ptr, 
   if (!(lr > 0.0f) || !isfinite(lr)) return fail(ctx, OPEN_E_INVALID, "learning rate must be finite and > 0");
   OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
   open_status st;
-  // gather buffers sized for the longest possible batch: batch rows of at most n entries
-  if ((st = mlp_batch_buffers(p, batch, (int64_t)batch * p->n))) return st;
-  if ((st = mlp_forward_batch(p, batch, rows, row_ptr, col, val, p->out))) return st;
-  if ((st = mlp_backward_batch(p, batch, rows, row_ptr, col, val, target, p->loss, loss_out, 0))) return st;
-  p->step += 1;
-  const float c1 = 1.0f - powf(0.9f, (float)p->step), c2 = 1.0f - powf(0.999f, (float)p->step);
-  OPEN_LAUNCH(ctx, "mlp_adam", k_adam, dim3(1024), dim3(256), 0, p->np, p->w, p->g, p->am, p->av, lr, c1, c2);
-  return mlp_repack(p);
+  if ((st = mlp_batch_buffers(p, batch))) return st;
+  return mlp_step(p, batch, rows, row_ptr, col, val, target, lr, loss_out, nullptr);
+}
+
+open_status open_mlp_train(open_mlp *p, int64_t m, const int64_t *row_ptr, const int32_t *col, const float *val,
+                           const float *target, int32_t batch, float lr, int32_t epochs, uint64_t seed,
+                           float *loss_hist) {
+  if (!p) return OPEN_E_INVALID;
+  open_ctx *ctx = p->ctx;
+  if (m <= 0 || m >= INT32_MAX || !row_ptr || !col || !val || !target)
+    return fail(ctx, OPEN_E_INVALID, "bad shape or pointer");
+  if (batch <= 0 || batch > kMaxBatchRows || batch > m)
+    return fail(ctx, OPEN_E_INVALID, "batch must be in [1, min(16384, m)]");
+  if (epochs < 0) return fail(ctx, OPEN_E_INVALID, "epochs must be >= 0");
+  if (!(lr > 0.0f) || !isfinite(lr)) return fail(ctx, OPEN_E_INVALID, "learning rate must be finite and > 0");
+  if (epochs == 0) return OPEN_OK;
+  OPEN_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int64_t spe = m / batch;  // full batches per epoch; the remainder is left to later shuffles
+  const int64_t total = spe * epochs;
+  int h = 1;
+  while (h < 31 && (int64_t(1) << (2 * h)) < m) ++h;
+  open_status st;
+  if ((st = mlp_batch_buffers(p, batch))) return st;
+  int64_t *perm = nullptr, *rows = nullptr;
+  float *losses = nullptr;
+  int64_t *t0h = nullptr;
+  if (hipMalloc(&perm, sizeof(int64_t) * (size_t)m) || hipMalloc(&rows, sizeof(int64_t) * (size_t)batch) ||
+      hipMalloc(&losses, sizeof(float) * (size_t)total)) {
+    (void)hipGetLastError();
+    (void)hipFree(perm);
+    (void)hipFree(rows);
+    (void)hipFree(losses);
+    return fail(ctx, OPEN_E_NOMEM, "training buffers");
+  }
+  // the per-step losses are indexed by the Adam step count, which may not start at zero
+  if ((st = pinned_get(ctx, 64, (void **)&t0h))) {
+    (void)hipFree(perm);
+    (void)hipFree(rows);
+    (void)hipFree(losses);
+    return st;
+  }
+  if (hipMemcpyAsync(t0h, p->tstate, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    (void)hipFree(perm);
+    (void)hipFree(rows);
+    (void)hipFree(losses);
+    return fail(ctx, OPEN_E_DEVICE, "reading the step counter");
+  }
+  const int64_t t0 = t0h[0];
+  float *loss_rec = losses - t0;  // loss of Adam step t lands in losses[t - t0]
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto one_step = [&]() -> open_status {
+    OPEN_LAUNCH(ctx, "mlp_rows_of_step", k_rows_of_step, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, perm,
+                batch, p->tstate, rows);
+    return mlp_step(p, batch, rows, row_ptr, col, val, target, lr, nullptr, loss_rec);
+  };
+  const int64_t sblocks = (m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096;
+  for (int32_t e = 0; e < epochs && st == OPEN_OK; ++e) {
+    OPEN_LAUNCH(ctx, "mlp_shuffle", k_shuffle, dim3((unsigned)sblocks), dim3(256), 0, m, h, seed, (int64_t)e, perm,
+                p->tstate);
+    for (int64_t b = 0; b < spe && st == OPEN_OK; ++b) {
+      if (!exec) {
+        // the first step runs eagerly (it sizes every workspace), the next one is recorded
+        if ((st = one_step())) break;
+        if (b + 1 < spe || e + 1 < epochs) {
+          if ((st = graph_capture(ctx, one_step, &graph))) break;
+          if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(ctx, OPEN_E_DEVICE, "graph instantiation failed");
+          }
+        }
+        continue;
+      }
+      if (hipGraphLaunch(exec, ctx->stream) != hipSuccess) st = fail(ctx, OPEN_E_DEVICE, "graph launch failed");
+    }
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st == OPEN_OK && loss_hist) {
+    float *hl = new (std::nothrow) float[(size_t)total];
+    if (!hl) {
+      st = fail(ctx, OPEN_E_NOMEM, "loss history");
+    } else {
+      if (hipMemcpyAsync(hl, losses, sizeof(float) * (size_t)total, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        st = fail(ctx, OPEN_E_DEVICE, "reading the losses");
+      } else {
+        for (int32_t e = 0; e < epochs; ++e) {
+          double sum = 0.0;
+          for (int64_t b = 0; b < spe; ++b) sum += hl[e * spe + b];
+          loss_hist[e] = (float)(sum / (double)spe);
+        }
+      }
+      delete[] hl;
+    }
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(perm);
+  (void)hipFree(rows);
+  (void)hipFree(losses);
+  return st;
 }
 
 open_status open_mlp_foldin(open_mlp *p, const float *F, int64_t m, const int64_t *row_ptr, const int32_t *col,
@@ -873,24 +1241,26 @@ open_status open_mlp_foldin(open_mlp *p, const float *F, int64_t m, const int64_
   uint8_t *f = used_fallback ? used_fallback : p->flag;
   // network, residual and fallback flag in one persistent kernel
   const int64_t tiles = (m + kIR - 1) / kIR;
-  const unsigned grid = (unsigned)(tiles < (int64_t)ctx->num_cu * 2 ? tiles : (int64_t)ctx->num_cu * 2);
+  // resident blocks per CU: three (LDS about 50 KB each) up to rank 32, two at rank 64
+  const int64_t per_cu = p->k == 64 ? 2 : 3;
+  const unsigned grid = (unsigned)(tiles < (int64_t)ctx->num_cu * per_cu ? tiles : (int64_t)ctx->num_cu * per_cu);
   const float *W = p->w;
   switch (p->k) {
     case 8:
-      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<8>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
-                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<8>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1p,
+                  W + p->off_b1, p->w2p, W + p->off_b2, p->w3p, W + p->off_b3, F, tau, U_out, r, f);
       break;
     case 16:
-      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<16>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
-                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<16>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1p,
+                  W + p->off_b1, p->w2p, W + p->off_b2, p->w3p, W + p->off_b3, F, tau, U_out, r, f);
       break;
     case 32:
-      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<32>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
-                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<32>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1p,
+                  W + p->off_b1, p->w2p, W + p->off_b2, p->w3p, W + p->off_b3, F, tau, U_out, r, f);
       break;
     default:
-      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<64>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1t,
-                  W + p->off_b1, W + p->off_w2, W + p->off_b2, W + p->off_w3, W + p->off_b3, F, tau, U_out, r, f);
+      OPEN_LAUNCH(ctx, "mlp_infer", k_mlp_infer<64>, dim3(grid), dim3(256), 0, m, row_ptr, col, val, p->n, p->w1p,
+                  W + p->off_b1, p->w2p, W + p->off_b2, p->w3p, W + p->off_b3, F, tau, U_out, r, f);
       break;
   }
   // re-solve the flagged rows with the ridge fold-in (only they are bucketed)

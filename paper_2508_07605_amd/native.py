@@ -50,7 +50,7 @@ SIGNATURES = {
     "open_objective": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _F32, _I32, _P]),
     "open_residual": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "open_predict": (_I32, [_P, _P, _I64, _P, _I32, _I32, _P, _P, _P, _I32, _F32, _P, _P, _P]),
-    "open_mlp_create": (_I32, [_P, ctypes.POINTER(_P), _I32, _I32, _I32, _P]),
+    "open_mlp_create": (_I32, [_P, ctypes.POINTER(_P), _I32, _I32, _I32, _P, ctypes.c_uint64]),
     "open_mlp_destroy": (_I32, [_P]),
     "open_mlp_num_params": (_I64, [_I32, _I32, _I32]),
     "open_mlp_get_weights": (_I32, [_P, _P]),
@@ -58,6 +58,7 @@ SIGNATURES = {
     "open_mlp_forward": (_I32, [_P, _I64, _P, _P, _P, _P]),
     "open_mlp_loss_grad": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     "open_mlp_train_step": (_I32, [_P, _I64, _P, _P, _P, _P, _P, _I32, _F32, _P]),
+    "open_mlp_train": (_I32, [_P, _I64, _P, _P, _P, _P, _I32, _F32, _I32, ctypes.c_uint64, _P]),
     "open_mlp_foldin": (_I32, [_P, _P, _I64, _P, _P, _P, _F32, _F32, _I32, _P, _P, _P, _P]),
 }
 
@@ -371,7 +372,7 @@ def open_mlp_num_params(n, k, hidden=256):
 class Surrogate:
     """open_mlp handle: the fold-in surrogate network."""
 
-    def __init__(self, ctx, n, k, hidden=256, init=None):
+    def __init__(self, ctx, n, k, hidden=256, init=None, seed=0):
         import numpy as np
         self.ctx, self.n, self.k, self.hidden = ctx, n, k, hidden
         self.num_params = open_mlp_num_params(n, k, hidden)
@@ -382,7 +383,8 @@ class Surrogate:
                 raise ValueError("init holds %d values, needs %d" % (buf.size, self.num_params))
         h = ctypes.c_void_p()
         ctx.check(lib().open_mlp_create(ctx.handle, ctypes.byref(h), n, k, hidden,
-                                        buf.ctypes.data_as(ctypes.c_void_p) if buf is not None else None))
+                                        buf.ctypes.data_as(ctypes.c_void_p) if buf is not None else None,
+                                        int(seed)))
         self.handle = h
 
     def get_weights(self):
@@ -426,6 +428,19 @@ class Surrogate:
                                                  _dev(target, torch.float32, "target", m * self.k),
                                                  _dev(rows, torch.int64, "rows"), int(batch), float(lr),
                                                  _dev(loss_out, torch.float32, "loss_out", 1)))
+
+    def train(self, row_ptr, col, val, target, batch, lr, epochs, seed=0):
+        """open_mlp_train: epochs of seeded on-device shuffles, one Adam step per full batch;
+        returns the mean batch loss of each epoch (numpy float32)."""
+        import numpy as np
+        m = row_ptr.numel() - 1
+        hist = np.zeros(max(int(epochs), 1), dtype=np.float32)
+        self.ctx.check(lib().open_mlp_train(self.handle, m, _dev(row_ptr, torch.int64, "row_ptr", m + 1),
+                                            _dev(col, torch.int32, "col"), _dev(val, torch.float32, "val"),
+                                            _dev(target, torch.float32, "target", m * self.k), int(batch),
+                                            float(lr), int(epochs), int(seed),
+                                            hist.ctypes.data_as(ctypes.c_void_p)))
+        return hist[:int(epochs)]
 
     def foldin(self, F, row_ptr, col, val, tau, lam, weighted=True, U_out=None, used_fallback=None, rho=None,
                count=True):

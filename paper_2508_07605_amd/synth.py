@@ -276,11 +276,14 @@ CONFIGS = {
     # same, exponent tuned so the density is 5 %
     "fit_d5": dict(cfg_id=6, n_cpu=24, n_gpu=20, k=32, lam=0.05, sweeps=15, m=200_000,
                    counts=("zipf", 1.6824, 3, 480)),
-    # 1M new apps with 4..24 observed settings each against fixed 480 x 32 setting factors
-    "foldin": dict(cfg_id=3, n_cpu=24, n_gpu=20, k=32, lam=0.05, m=1_000_000, counts=("uniform", 4, 24)),
-    # surrogate 960 -> 256 -> 256 -> 32 trained on 2M fold-ins of the same generator (other seed)
-    "surrogate": dict(cfg_id=3, n_cpu=24, n_gpu=20, k=32, lam=0.05, m_train=2_000_000, train_seed=1,
-                      hidden=256, batch=4096, lr=1e-3, tau=0.02, counts=("uniform", 4, 24)),
+    # 1M new apps with 4..24 observed settings each against fixed 480 x 32 setting factors; the
+    # fold-in of a new row is the plain ridge solution (lambda I, weighted=False)
+    "foldin": dict(cfg_id=3, n_cpu=24, n_gpu=20, k=32, lam=0.05, weighted=False, m=1_000_000,
+                   counts=("uniform", 4, 24)),
+    # surrogate 960 -> 256 -> 256 -> 32 trained for 10 epochs on 2M fold-ins of the same generator
+    # (other seed)
+    "surrogate": dict(cfg_id=3, n_cpu=24, n_gpu=20, k=32, lam=0.05, weighted=False, m_train=2_000_000, train_seed=1,
+                      hidden=256, batch=4096, lr=1e-3, epochs=10, tau=0.02, counts=("uniform", 4, 24)),
     # 2M apps x 1920 settings, ~2 % density, rank 64
     "large": dict(cfg_id=5, n_cpu=48, n_gpu=40, k=64, lam=0.05, sweeps=10, m=2_000_000,
                   counts=("zipf", 1.6931, 3, 1920), gamma=0.05, batch=16384, hidden=256),

@@ -135,3 +135,135 @@ def test_fallback_limits_and_middle(ctx, data):
     assert np.array_equal(used, ~(rho <= tau)) and nfm == used.sum()
     assert np.array_equal(Um[used], als[used]) and np.array_equal(Um[~used], fwd[~used])
     net.close()
+
+
+def mix64(z):
+    # SplitMix64 output function on uint64 arrays (wrapping arithmetic)
+    with np.errstate(over="ignore"):
+        z = np.asarray(z, dtype=np.uint64) + np.uint64(0x9e3779b97f4a7c15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xbf58476d1ce4e5b9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94d049bb133111eb)
+        return z ^ (z >> np.uint64(31))
+
+
+def feistel_order(m, seed, epoch):
+    # the training order the header defines: four Feistel rounds on 2h-bit integers (4^h >= m),
+    # walked along the cycle until the value is below m
+    h = 1
+    while (1 << (2 * h)) < m:
+        h += 1
+    with np.errstate(over="ignore"):
+        base = mix64(np.uint64(seed)) + np.uint64(4 * epoch)
+    keys = [mix64(base + np.uint64(r)) for r in range(4)]
+    mask = np.uint64((1 << h) - 1)
+    x = np.arange(m, dtype=np.uint64)
+    out = np.empty(m, dtype=np.uint64)
+    todo = np.arange(m)
+    while todo.size:
+        L, R = x[todo] >> np.uint64(h), x[todo] & mask
+        for kr in keys:
+            L, R = R, L ^ (mix64(R ^ kr) & mask)
+        y = (L << np.uint64(h)) | R
+        x[todo] = y
+        done = y < np.uint64(m)
+        out[todo[done]] = y[done]
+        todo = todo[~done]
+    return out.astype(np.int64)
+
+
+def test_feistel_order_is_a_permutation():
+    for m in (1, 2, 3, 5, 1000, 4099, 65537):
+        p = feistel_order(m, 7, 3)
+        assert np.array_equal(np.sort(p), np.arange(m))
+    assert not np.array_equal(feistel_order(4099, 7, 0), feistel_order(4099, 7, 1))
+
+
+def test_train_equals_its_steps(ctx, data):
+    # open_mlp_train (device shuffle, eager first step, graph replays) against the same Adam
+    # steps taken one by one through open_mlp_train_step on the order computed here
+    grid, rows, V, target, params = data
+    drp, dcol, dval, dt = dev(rows.row_ptr), dev(rows.col), dev(rows.val), dev(target)
+    B, E, seed = 1000, 3, 11
+    a = native.Surrogate(ctx, N, K, H, init=pack(params))
+    hist = a.train(drp, dcol, dval, dt, B, 1e-3, E, seed=seed)
+    b = native.Surrogate(ctx, N, K, H, init=pack(params))
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    per_epoch = []
+    for e in range(E):
+        order = feistel_order(rows.m, seed, e)
+        ls = []
+        for s in range(rows.m // B):
+            b.train_step(drp, dcol, dval, dt, dev(order[s * B:(s + 1) * B]), 1e-3, loss_out=loss)
+            ls.append(float(loss.item()))
+        per_epoch.append(np.mean(np.asarray(ls, np.float64)))
+    wa, wb = a.get_weights(), b.get_weights()
+    print("train: epoch losses", hist, "steps", np.asarray(per_epoch, np.float32))
+    assert np.array_equal(wa, wb)
+    assert np.allclose(hist, per_epoch, rtol=1e-6)
+    assert hist[-1] < hist[0]
+    a.close()
+    b.close()
+
+
+def test_seeded_initial_weights(ctx):
+    a = native.Surrogate(ctx, N, K, H, seed=5).get_weights()
+    b = native.Surrogate(ctx, N, K, H, seed=5).get_weights()
+    c = native.Surrogate(ctx, N, K, H, seed=6).get_weights()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    for arr, fan in zip(unpack(a), [2 * N, 2 * N, H, H, H, H]):
+        bound = 1.0 / np.sqrt(fan)
+        assert np.abs(arr).max() <= bound
+        assert abs(arr.mean()) < 0.1 * bound and arr.std() > 0.5 * bound  # U(-a, a): sd a/sqrt 3
+
+
+def test_large_grid_rank64_network_and_fallback(ctx):
+    # the large grid's shape: 1920 settings (48 x 40 caps), rank 64, network 3840-256-256-64.
+    # Forward against the oracle, the fused inference against the batched forward bit for bit,
+    # and the fallback rows against the ridge fold-in, including rows of 1024 or more entries
+    # (solved by the primal rank-64 kernel in several chunks).
+    grid = synth.grid_of("large")
+    n, k = grid.n, 64
+    r = np.random.default_rng(64)
+    counts = np.concatenate([r.integers(3, 40, size=700), r.integers(33, 400, size=200), [1024, 1500, 1920, 0]])
+    r.shuffle(counts)
+    rp = np.zeros(len(counts) + 1, np.int64)
+    rp[1:] = np.cumsum(counts)
+    col = np.concatenate([np.sort(r.choice(n, size=c, replace=False)) for c in counts]).astype(np.int32)
+    val = r.uniform(0.4, 1.0, size=int(rp[-1])).astype(np.float32)
+    V = synth.setting_factors(5, grid, k, m_ref=1024)
+    params = synth.mlp_init(5, (2 * n, H, H, k), seed=2)
+    net = native.Surrogate(ctx, n, k, H, init=pack(params))
+    drp, dcol, dval, dV = dev(rp), dev(col), dev(val), dev(V)
+    fwd = net.forward(drp, dcol, dval).cpu().numpy()
+    sub = np.arange(0, len(counts), 7)
+    Xs = omlp.dense_input(np.concatenate([[0], np.cumsum(counts[sub])]),
+                          np.concatenate([col[rp[i]:rp[i + 1]] for i in sub]),
+                          np.concatenate([val[rp[i]:rp[i + 1]] for i in sub]), n)
+    ref, _ = omlp.forward(params, Xs)
+    ef = fro(fwd[sub], ref)
+    print("rank 64 forward rel %.2e" % ef)
+    assert ef <= 1e-2
+    Uinf, nfi = net.foldin(dV, drp, dcol, dval, float("inf"), 0.05, False)
+    assert nfi == 0 and np.array_equal(Uinf.cpu().numpy(), fwd)
+    als = native.open_foldin(ctx, dV, drp, dcol, dval, 0.05, False).cpu().numpy()
+    rho = torch.empty(len(counts), dtype=torch.float32, device="cuda")
+    used = torch.empty(len(counts), dtype=torch.uint8, device="cuda")
+    net.foldin(dV, drp, dcol, dval, float("inf"), 0.05, False, rho=rho)
+    tau = float(np.median(rho.cpu().numpy()[counts > 0]))
+    Um, nfm = net.foldin(dV, drp, dcol, dval, tau, 0.05, False, used_fallback=used, rho=rho)
+    Um, used = Um.cpu().numpy(), used.cpu().numpy().astype(bool)
+    ref_als, _ = oracle.ridge_rows(rp, col, val, V, 0.05, False)
+    e = np.linalg.norm(Um[used] - ref_als[used], axis=1) / np.linalg.norm(ref_als[used], axis=1)
+    print("rank 64 fallback rows %d (long rows among them %d): max rel err vs oracle %.2e"
+          % (used.sum(), (used & (counts >= 1024)).sum(), e.max()))
+    assert e.max() <= 1e-4
+    assert np.array_equal(Um[~used], fwd[~used])
+    # every row re-solved: the long rows through the fallback path against the oracle
+    U0, nf0 = net.foldin(dV, drp, dcol, dval, 0.0, 0.05, False)
+    U0 = U0.cpu().numpy()
+    assert nf0 == int((counts > 0).sum())
+    long_rows = counts >= 1024
+    e0 = np.linalg.norm(U0[long_rows] - ref_als[long_rows], axis=1) / np.linalg.norm(ref_als[long_rows], axis=1)
+    print("rank 64 rows of 1024+ entries via the fallback: max rel err %.2e" % e0.max())
+    assert e0.max() <= 1e-4
+    net.close()
