@@ -170,9 +170,13 @@ def surrogate_leg(args, ctx, dV, drp, dcol, dval, m, steps, warmup, log, als_ms)
     return out, U
 
 
-def predict_leg(ctx, steps, warmup, log):
-    """Fused predict + Algorithm 2 selection on 2M apps x 1920 settings (48 x 40 caps), rank 64:
-    the prediction tile U V^T on FP32 MFMA and the per-row selection, P not written."""
+def large_leg(args, ctx, steps, warmup, log):
+    """The large grid: 2M apps x 1920 settings (48 x 40 caps), ~2 % observed (truncated Zipf on
+    [3, 1920]), rank 64.  ALS-WR fit of 10 sweeps from the generator's initial factors (time per
+    sweep), then the fused predict + Algorithm 2 selection over all 1920 settings of every app
+    with the fitted factors, then the surrogate 3840-256-256-64 trained at batch 16384 on the
+    fold-ins of the fitted apps against the fitted setting factors, used with the ridge fallback
+    on 200k new apps."""
     import numpy as np
     import torch
 
@@ -180,17 +184,51 @@ def predict_leg(ctx, steps, warmup, log):
 
     c = synth.CONFIGS["large"]
     grid = synth.grid_of("large")
-    k, m = c["k"], c["m"]
-    t0 = time.time()
-    V = synth.setting_factors(c["cfg_id"], grid, k)
-    U = synth.latent_rows(c["cfg_id"], grid, V, m, seed=0)
+    k, lam, m = c["k"], c["lam"], c["m"]
     dev = torch.device("cuda", 0)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    dU, dV = to(U), to(V)
+    t0 = time.time()
+    rows = synth.draw_rows(c["cfg_id"], grid, m, c["counts"], seed=0)
+    U0, V0 = synth.init_factors(c["cfg_id"], m, grid.n, k)
+    drp, dcol, dval = to(rows.row_ptr), to(rows.col), to(rows.val)
+    log("large: %d apps x %d settings, %d observed, generated in %.1f s" % (m, grid.n, rows.nnz, time.time() - t0))
+    out = {}
+
+    # ---- fit
+    dU, dV = to(U0), to(V0)
+
+    def timed_fit(sweeps):
+        dU.copy_(to(U0))
+        dV.copy_(to(V0))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        native.open_fit(ctx, drp, dcol, dval, dU, dV, lam, sweeps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    timed_fit(1)  # warm-up (workspaces, code)
+    t1 = timed_fit(1)
+    S = c["sweeps"]
+    tS = timed_fit(S)
+    ms = (tS - t1) / (S - 1)
+    obj = native.open_objective(ctx, drp, dcol, dval, dU, dV, lam)
+    ccount = np.bincount(rows.col, minlength=grid.n)
+    flops = float(row_flops(rows.counts(), k).sum() + row_flops(ccount, k).sum())
+    tf = flops / (ms * 1e-3) / 1e12
+    out["fit"] = {"workload": "ALS-WR fit: %d apps x %d settings (48 x 40 caps), %d observed (truncated Zipf 1.6931 on "
+                              "[3, 1920]), rank %d, weighted lambda %g, %d sweeps" % (m, grid.n, rows.nnz, k, lam, S),
+                  "ms_per_sweep": ms, "ms_total_%d_sweeps" % S: tS, "setup_ms_per_call": t1 - ms,
+                  "objective_after": obj,
+                  "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops}}
+    log("large fit: %.3f ms per sweep (%.1f TFLOP/s), objective %.6g" % (ms, tf, obj))
+
+    # ---- predict + Algorithm 2 with the fitted factors
     cc, cg = to(grid.cpu_w.astype(np.float32)), to(grid.gpu_w.astype(np.float32))
     bi = torch.empty(m, dtype=torch.int32, device=dev)
     bs = torch.empty(m, dtype=torch.float32, device=dev)
-    log("predict: inputs %d x %d, rank %d in %.1f s" % (m, grid.n, k, time.time() - t0))
     run = lambda: native.open_predict(ctx, dU, dV, cc, cg, grid.base, c["gamma"], best_idx=bi, best_saving=bs)
     for _ in range(warmup):
         run()
@@ -201,16 +239,84 @@ def predict_leg(ctx, steps, warmup, log):
         run()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    flops = 2.0 * k * grid.n * m
-    byts = (4.0 * k + 8.0) * m
-    tf = flops / (ms * 1e-3) / 1e12
-    return {"workload": "predict + Alg. 2 selection: %d apps x %d settings (48 x 40 caps), rank %d, gamma %g"
-                        % (m, grid.n, k, c["gamma"]),
-            "rows_per_s": m / (ms * 1e-3), "ms_per_step": ms,
-            "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops,
-                         "algorithmic_bytes": byts, "hbm_gbs": round(byts / (ms * 1e-3) / 1e9, 1)}}
+    pms = e0.elapsed_time(e1) / steps
+    pflops = 2.0 * k * grid.n * m
+    pbytes = (4.0 * k + 8.0) * m
+    ptf = pflops / (pms * 1e-3) / 1e12
+    out["predict_select"] = {
+        "workload": "predict + Alg. 2 selection with the fitted factors: %d apps x %d settings, rank %d, gamma %g"
+                    % (m, grid.n, k, c["gamma"]),
+        "rows_per_s": m / (pms * 1e-3), "ms_per_step": pms,
+        "chosen_not_baseline_fraction": float((bi != grid.base).float().mean().item()),
+        "mean_saving": float(bs.mean().item()),
+        "roofline": {"bound": "mfma", "achieved": round(ptf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ptf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": pflops,
+                     "algorithmic_bytes": pbytes, "hbm_gbs": round(pbytes / (pms * 1e-3) / 1e9, 1)}}
+    log("large predict+select %.3e rows/s, %.1f TFLOP/s" % (m / (pms * 1e-3), ptf))
+    del bi, bs
+
+    # ---- surrogate at rank 64, batch 16384, with the ridge fallback
+    if not args.no_surrogate:
+        wt, tau, B, E = False, 0.02, c["batch"], int(args.surrogate_epochs)
+        target = native.open_foldin(ctx, dV, drp, dcol, dval, lam, wt)
+        net = native.Surrogate(ctx, grid.n, k, c["hidden"], seed=1)
+        untrained = native.Surrogate(ctx, grid.n, k, c["hidden"], seed=1)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        hist = net.train(drp, dcol, dval, target, B, 1e-3, E, seed=7)
+        torch.cuda.synchronize()
+        train_s = time.time() - t0
+        nsteps = E * (m // B)
+        log("large surrogate: %d epochs (%d steps at batch %d) in %.2f s; epoch losses %s"
+            % (E, nsteps, B, train_s, np.array2string(hist, precision=3)))
+        del target
+        new = synth.draw_rows(c["cfg_id"], grid, 200_000, c["counts"], seed=1)
+        nrp, ncol, nval = to(new.row_ptr), to(new.col), to(new.val)
+        Un = torch.empty((new.m, k), dtype=torch.float32, device=dev)
+
+        def timed(fn):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+
+        ms_als = timed(lambda: native.open_foldin(ctx, dV, nrp, ncol, nval, lam, wt, U_out=Un))
+        Ua = Un.clone()
+        ms_u = timed(lambda: untrained.foldin(dV, nrp, ncol, nval, tau, lam, wt, U_out=Un, count=False))
+        _, nf_u = untrained.foldin(dV, nrp, ncol, nval, tau, lam, wt, U_out=Un)
+        ms_t = timed(lambda: net.foldin(dV, nrp, ncol, nval, tau, lam, wt, U_out=Un, count=False))
+        _, nf_t = net.foldin(dV, nrp, ncol, nval, tau, lam, wt, U_out=Un)
+        # RMSE against the noiseless truth on unobserved settings of 5,000 new apps
+        ev = np.arange(0, new.m, 40)
+        T = synth.truth_dense(new.apps.take(ev), grid)
+        obs = np.zeros_like(T, dtype=bool)
+        for j, i in enumerate(ev):
+            obs[j, new.col[new.row_ptr[i]:new.row_ptr[i + 1]]] = True
+        Vd = dV.cpu().numpy().astype(np.float64)
+        idx = torch.from_numpy(ev).to(dev)
+        rm = lambda U: float(np.sqrt((((U[idx].cpu().numpy().astype(np.float64) @ Vd.T) - T)[~obs] ** 2).mean()))
+        r_s, r_a = rm(Un), rm(Ua)
+        out["surrogate"] = {
+            "workload": "surrogate fold-in + ridge fallback on 200000 new apps of the large grid: network %d-%d-%d-%d "
+                        "trained %d epochs at batch %d on the fold-ins of the %d fitted apps, tau %g, plain lambda %g"
+                        % (2 * grid.n, c["hidden"], c["hidden"], k, E, B, m, tau, lam),
+            "rows_per_s": new.m / (ms_t * 1e-3), "fallback_fraction": nf_t / new.m,
+            "untrained_rows_per_s": new.m / (ms_u * 1e-3), "untrained_fallback_fraction": nf_u / new.m,
+            "als_rows_per_s": new.m / (ms_als * 1e-3), "train_seconds": round(train_s, 3),
+            "train_ms_per_step": round(1e3 * train_s / max(nsteps, 1), 4), "epoch_loss": [float(x) for x in hist],
+            "rmse": r_s, "rmse_gpu_als": r_a, "rmse_gap_vs_gpu_als": abs(r_s - r_a)}
+        log("large surrogate+fallback %.3e rows/s (fallback %.3f), untrained %.3e (fallback %.3f), ALS %.3e; "
+            "RMSE %.5f vs ALS %.5f" % (new.m / (ms_t * 1e-3), nf_t / new.m, new.m / (ms_u * 1e-3), nf_u / new.m,
+                                       new.m / (ms_als * 1e-3), r_s, r_a))
+        net.close()
+        untrained.close()
+    return out
 
 
 def phase_leg(ctx, steps, warmup, log):
@@ -440,7 +546,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time the pass as one HIP graph replay instead of "
                                                           "kernel-by-kernel launches")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate (MLP + fallback) leg")
-    ap.add_argument("--no-predict", action="store_true", help="skip the predict + selection leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-grid leg (fit, predict + selection, "
+                                                              "rank-64 surrogate)")
     ap.add_argument("--no-fit", action="store_true", help="skip the ALS fit leg")
     ap.add_argument("--no-phase", action="store_true", help="skip the Alg. 1 phase-detection leg")
     ap.add_argument("--no-predictor", action="store_true", help="skip the offline performance predictor leg")
@@ -581,10 +688,8 @@ def main():
     }
 
     log = lambda msg: print("bench: " + msg, file=sys.stderr, flush=True)
-    if not args.no_predict:
-        out["predict_select"] = predict_leg(ctx, args.steps, args.warmup, log)
-        log("predict+select %.3e rows/s, %.1f TFLOP/s" % (out["predict_select"]["rows_per_s"],
-                                                          out["predict_select"]["roofline"]["achieved"]))
+    if not args.no_large:
+        out["large"] = large_leg(args, ctx, args.steps, args.warmup, log)
     if not args.no_phase:
         out["phase_detect"] = phase_leg(ctx, args.steps, args.warmup, log)
         log("phase detection %.3e traces/s, %.0f GB/s" % (out["phase_detect"]["traces_per_s"],

@@ -813,9 +813,14 @@ static int wgrad_slices(int64_t B, int M, int N, int *kc) {
   return (int)((B + c - 1) / c);
 }
 
+// partial floats of an M x N weight gradient for any batch of at most B rows (the slice count
+// does not grow with B, but a smaller batch can take up to its target count)
 static int64_t wgrad_part_floats(int64_t B, int M, int N) {
-  int kc;
-  return (int64_t)wgrad_slices(B, M, N, &kc) * ((int64_t)M * N + M);
+  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  int64_t S = (1024 + tiles - 1) / tiles;
+  if (S > 256) S = 256;
+  const int64_t smax = (B + 31) / 32;  // slices are at least 32 rows
+  return (S < smax ? S : smax) * ((int64_t)M * N + M);
 }
 
 static void mlp_free_batch(open_mlp *p) {
