@@ -391,10 +391,15 @@ def predictor_leg(ctx, rows, grid, steps, warmup, log):
 
 
 def ncf_leg(ctx, steps, warmup, log):
-    """NCF fold-in (SELU network, embedding learned by 30 gradient steps per new app, products
-    on FP32 MFMA) for 65,536 new apps with 4-24 observed settings each: apps per second.  Algorithmic work per
-    observed entry and step: forward 2 (32*64 + 64*64 + 64) flop, backward 2 (64 + 64*64)
-    flop, plus 2*32*64 flop per app and step for the embedding layer both ways."""
+    """NCF (Section III-B.1 model): trained on the GPU (open_ncf_train, 20 epochs, 8 applications
+    x 480 settings per batch, Adam 1e-3) on the dense offline matrix of the 4096 reference apps
+    (the same noiseless matrix whose truncated SVD gives the ALS setting factors); then the
+    NCF fold-in (embedding learned by 30 gradient steps per new app, products on FP32 MFMA)
+    of 65,536 new apps with 4-24 observed settings each: apps per second, and the RMSE of NCF
+    and of the plain-lambda ALS fold-in against the noiseless truth on unobserved settings of
+    20,000 of them.  Algorithmic work per observed entry and step of the fold-in: forward
+    2 (32*64 + 64*64 + 64) flop, backward 2 (64 + 64*64) flop, plus 2*32*64 flop per app and
+    step for the embedding layer both ways."""
     import numpy as np
     import torch
 
@@ -402,31 +407,69 @@ def ncf_leg(ctx, steps, warmup, log):
 
     c = synth.NCF
     grid = synth.grid_of("foldin")
+    dev = torch.device("cuda", 0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    # offline training
+    m_off = 4096
+    R = synth.truth_dense(synth.draw_apps(synth.rng(3, synth.S_REF, 0), m_off), grid).astype(np.float32)
+    p0 = synth.ncf_params(3, grid.n)
+    S0 = p0.pop("S")
+    flat = to(native.ncf_pack(np.zeros((m_off, 32), np.float32), S0, p0))
+    dR = to(R)
+    G, E_train = 8, 20
+    torch.cuda.synchronize()
+    t0 = time.time()
+    hist = native.open_ncf_train(ctx, dR, flat, G, 1e-3, E_train, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    nsteps = E_train * (m_off // G)
+    log("NCF training: %d epochs (%d steps of %d entries) in %.2f s, epoch losses %s"
+        % (E_train, nsteps, G * grid.n, train_s, np.array2string(hist, precision=5)))
+    _, S, net = native.ncf_unpack(flat, m_off, grid.n)
+    # fold-in of new apps
     m = 65_536
     rows = synth.draw_rows(3, grid, m, ("uniform", 4, 24), seed=0)
-    p = synth.ncf_params(3, grid.n)
-    S = torch.from_numpy(p.pop("S")).cuda()
-    dp = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
-    drp, dcol, dval = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (rows.row_ptr, rows.col, rows.val))
-    E = torch.empty((m, 32), dtype=torch.float32, device=S.device)
-    L = torch.empty(m, dtype=torch.float32, device=S.device)
+    drp, dcol, dval = to(rows.row_ptr), to(rows.col), to(rows.val)
+    E = torch.empty((m, 32), dtype=torch.float32, device=dev)
+    L = torch.empty(m, dtype=torch.float32, device=dev)
     reps = max(1, steps // 4)
     for _ in range(max(1, warmup // 2)):
-        native.open_ncf_foldin(ctx, S, dp, drp, dcol, dval, c["steps"], c["eta"], c["mu"], E_out=E, loss_out=L)
+        native.open_ncf_foldin(ctx, S, net, drp, dcol, dval, c["steps"], c["eta"], c["mu"], E_out=E, loss_out=L)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        native.open_ncf_foldin(ctx, S, dp, drp, dcol, dval, c["steps"], c["eta"], c["mu"], E_out=E, loss_out=L)
+        native.open_ncf_foldin(ctx, S, net, drp, dcol, dval, c["steps"], c["eta"], c["mu"], E_out=E, loss_out=L)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     nnz = float(rows.nnz)
     flops = c["steps"] * (nnz * 2 * (32 * 64 + 64 * 64 + 64 + 64 + 64 * 64) + m * 2 * 2 * 32 * 64)
     tf = flops / (ms * 1e-3) / 1e12
-    return {"workload": "NCF fold-in: %d new apps x 480 settings, 4-24 observed, embedding 32, SELU 64-64, "
-                        "%d gradient steps" % (m, c["steps"]),
+    # accuracy of NCF and ALS on 20,000 of the new apps (unobserved settings, noiseless truth)
+    ev = np.arange(20_000)
+    T = synth.truth_dense(rows.apps.take(ev), grid)
+    obs = np.zeros_like(T, dtype=bool)
+    for i in ev:
+        obs[i, rows.col[rows.row_ptr[i]:rows.row_ptr[i + 1]]] = True
+    with torch.no_grad():
+        Ee = E[:len(ev)].double()
+        X1 = torch.cat([Ee[:, None, :].expand(-1, grid.n, -1), S.double()[None].expand(len(ev), -1, -1)], dim=2)
+        selu = lambda z: 1.0507009873554805 * torch.where(z > 0, z, 1.6732632423543772 * torch.expm1(torch.clamp(z, max=0)))
+        h1 = selu(X1 @ net["W1"].double().T + net["b1"].double())
+        h2 = selu(h1 @ net["W2"].double().T + net["b2"].double())
+        P_ncf = (h2 @ net["w3"].double() + net["b3"].double()[0]).cpu().numpy()
+    V = synth.setting_factors(3, grid, 32)
+    cf = synth.CONFIGS["foldin"]
+    Ua = native.open_foldin(ctx, to(V), drp, dcol, dval, cf["lam"], cf["weighted"])[:len(ev)].cpu().numpy()
+    P_als = Ua.astype(np.float64) @ V.astype(np.float64).T
+    rmse = lambda P: float(np.sqrt(((P - T)[~obs] ** 2).mean()))
+    return {"workload": "NCF: trained %d epochs on the 4096 x 480 reference matrix (%.2f s, %.3f ms per step of %d "
+                        "entries); fold-in of %d new apps x 480 settings, 4-24 observed, embedding 32, SELU 64-64, "
+                        "%d gradient steps" % (E_train, train_s, 1e3 * train_s / nsteps, G * grid.n, m, c["steps"]),
             "apps_per_s": m / (ms * 1e-3), "ms_per_call": ms, "mean_final_loss": float(L.mean().item()),
+            "train_epoch_loss": [float(x) for x in hist], "train_seconds": round(train_s, 3),
+            "rmse_ncf": rmse(P_ncf), "rmse_als_foldin": rmse(P_als),
             "roofline": {"bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tf / PEAK_FP32_TFLOPS, 4), "algorithmic_flops": flops}}
 
@@ -703,9 +746,10 @@ def main():
             out["perf_predictor"]["roofline"]["bf16_mfma_tflops"]))
     if not args.no_ncf:
         out["ncf_foldin"] = ncf_leg(ctx, args.steps, args.warmup, log)
-        log("NCF fold-in %.3e apps/s (%.3f ms), %.1f TFLOP/s" % (
+        log("NCF fold-in %.3e apps/s (%.3f ms), %.1f TFLOP/s; RMSE NCF %.5f vs ALS fold-in %.5f" % (
             out["ncf_foldin"]["apps_per_s"], out["ncf_foldin"]["ms_per_call"],
-            out["ncf_foldin"]["roofline"]["achieved"]))
+            out["ncf_foldin"]["roofline"]["achieved"], out["ncf_foldin"]["rmse_ncf"],
+            out["ncf_foldin"]["rmse_als_foldin"]))
     if not args.no_fit:
         fit_state, out["fit"] = fit_leg(args, ctx, log)
         out["refit"] = refit_leg(ctx, fit_state, log)

@@ -337,6 +337,31 @@ open_status open_ncf_foldin(open_ctx *ctx, const float *S, int32_t n, int32_t d,
                             const int64_t *row_ptr, const int32_t *col, const float *val, int32_t steps, float eta,
                             float mu, float *E_out, float *loss_out, int32_t *row_status);
 
+/*
+ * NCF offline training (Section III-B.1: the CF model learns from the profiled applications):
+ * the model above, application embeddings E included, fitted to a dense offline matrix R
+ * (m_off applications x n settings, every entry observed) by Adam (0.9, 0.999, 1e-8,
+ * bias-corrected) on the mean squared error over batches of whole applications (each batch
+ * entry pairs an application with one of its settings).  Epoch e visits the applications in
+ * the seeded device order that open_mlp_train uses (Feistel network, keys from seed and e);
+ * m_off / apps_per_batch batches per epoch.  The products run on BF16 MFMA with float32
+ * accumulation (float32 masters); the embedding gradients are summed in a fixed order.
+ *   R        device float32[m_off*n] row-major
+ *   params   device float32[open_ncf_num_params(m_off, n)], in/out, packed as
+ *            E[m_off][d], S[n][d], W1[64][2d], b1[64], W2[64][64], b2[64], w3[64], b3[1]
+ *            (d = 32); S, W1 ... b3 are the arguments of open_ncf_foldin
+ *   loss_hist HOST float32[epochs] or NULL: mean batch loss of each epoch
+ * apps_per_batch in [1, m_off] with apps_per_batch * n <= 2^20.  Synchronous.
+ */
+int64_t open_ncf_num_params(int64_t m_off, int32_t n);
+open_status open_ncf_train(open_ctx *ctx, int64_t m_off, int32_t n, int32_t d, const float *R, float *params,
+                           int32_t apps_per_batch, float lr, int32_t epochs, uint64_t seed, float *loss_hist);
+/* Loss and gradient (HOST float32[open_ncf_num_params], same packing) of one batch: the G
+ * distinct applications listed in apps (device int64[G]) with all n settings each; the
+ * parameters are not changed.  Synchronous. */
+open_status open_ncf_loss_grad(open_ctx *ctx, int64_t m_off, int32_t n, int32_t d, const float *R,
+                               const float *params, const int64_t *apps, int32_t G, double *loss, float *grads_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -151,6 +151,47 @@ def loss_rows(row_ptr, col, val, S, p, mu, E, rows=None):
     return out
 
 
+def train_loss_and_grads(E, S, p, apps, R):
+    """Offline training of the model on the dense offline matrix R (applications x settings,
+    every entry observed): the objective on a batch of whole applications (rows `apps` of R,
+    every setting of each),
+
+        L = (1/B) sum_{g, j} (y(E[apps[g]], S[j]) - R[apps[g], j])^2,   B = len(apps) * n,
+
+    and its gradient with respect to the application embeddings E, the setting embeddings S
+    and every network parameter, by the chain rule layer by layer backwards.  Returns
+    (L, {"E", "S", "W1", "b1", "W2", "b2", "w3", "b3"})."""
+    p = _f64(p)
+    E = np.asarray(E, dtype=np.float64)
+    S = np.asarray(S, dtype=np.float64)
+    apps = np.asarray(apps, dtype=np.int64)
+    n, d = S.shape
+    G = len(apps)
+    ai = np.repeat(apps, n)                 # application of each batch entry
+    sj = np.tile(np.arange(n), G)           # setting of each batch entry
+    r = np.asarray(R, dtype=np.float64)[ai, sj]
+    X = np.concatenate([E[ai], S[sj]], axis=1)
+    Z1 = X @ p["W1"].T + p["b1"]
+    H1 = selu(Z1)
+    Z2 = H1 @ p["W2"].T + p["b2"]
+    H2 = selu(Z2)
+    y = H2 @ p["w3"] + p["b3"][0]
+    B = len(r)
+    L = float(np.mean((y - r) ** 2))
+    dy = 2.0 * (y - r) / B
+    g = {"w3": H2.T @ dy, "b3": np.array([dy.sum()])}
+    dZ2 = dy[:, None] * p["w3"][None, :] * selu_grad(Z2)
+    g["W2"], g["b2"] = dZ2.T @ H1, dZ2.sum(axis=0)
+    dZ1 = (dZ2 @ p["W2"]) * selu_grad(Z1)
+    g["W1"], g["b1"] = dZ1.T @ X, dZ1.sum(axis=0)
+    dX = dZ1 @ p["W1"]
+    g["E"] = np.zeros_like(E)
+    np.add.at(g["E"], ai, dX[:, :d])
+    g["S"] = np.zeros_like(S)
+    np.add.at(g["S"], sj, dX[:, d:])
+    return L, g
+
+
 def ncf_params(S_shape_d=32, hidden=64):
     """Shapes of the network arrays (for documentation and tests)."""
     d = S_shape_d

@@ -19,6 +19,7 @@
 #include <new>
 
 #include "common.h"
+#include "dense.h"
 
 namespace openk {
 
@@ -48,6 +49,10 @@ __device__ __forceinline__ float erf_as(float x) {
   return __builtin_copysignf(__builtin_fmaf(-t * q, e, 1.0f), x);
 }
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+// SELU (Klambauer et al. 2017) and its derivative (the right-hand value at 0 is not taken: z > 0)
+constexpr float kSeluA = 1.6732632423543772f, kSeluL = 1.0507009873554805f;
+__device__ __forceinline__ float selu(float z) { return z > 0.f ? kSeluL * z : kSeluL * kSeluA * (__expf(z) - 1.f); }
+__device__ __forceinline__ float selu_grad(float z) { return z > 0.f ? kSeluL : kSeluL * kSeluA * __expf(z); }
 __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
@@ -163,7 +168,7 @@ __global__ __launch_bounds__(256) void k_layer1(int64_t B, const int64_t *__rest
 // C[m][n] = sum_k A(m, k) B(n, k), A(m, k) = A[m*sam + k*sak], B(n, k) = B[n*sbn + k*sbk],
 // float32 operands rounded to bfloat16 when staged in LDS, float32 accumulation.
 // Block tile 64 x 64, four wavefronts of 32 x 32 (v_mfma_f32_32x32x16_bf16), K chunks of 32.
-enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+
 
 // Operand staging of the BF16 MFMA products.  A 64-row tile of X(r, k) = X[r*sr + k*sk] is
 // staged one strip of up to kStripK k values at a time: every thread first issues all of its
@@ -175,9 +180,8 @@ constexpr int kStripK = 256;
 constexpr int kLdk = kStripK + 8;  // LDS row pitch in bf16 (pads banks)
 
 __device__ __forceinline__ void strip_load(float (&v)[8][8], const float *__restrict__ X, int64_t sr, int64_t sk,
-                                           int64_t r0, int64_t R, int k0, int Kd) {
+                                           int64_t r0, int64_t R, int k0, int Kd, bool kfast) {
   const int t = threadIdx.x;
-  const bool kfast = sk == 1;
   const int row = kfast ? t >> 2 : t & 63, kg = kfast ? t & 3 : t >> 6;
   const int64_t gr = r0 + row;
   const bool rok = gr < R;
@@ -235,8 +239,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int Kd, const float 
   for (int k0 = 0; k0 < Kd; k0 += kStripK) {
     const int klen = Kd - k0 < kStripK ? Kd - k0 : kStripK;
     float va[8][8], vb[8][8];
-    strip_load(va, A, sam, sak, m0, M, k0, Kd);
-    strip_load(vb, Bm, sbn, sbk, n0, N, k0, Kd);
+    strip_load(va, A, sam, sak, m0, M, k0, Kd, sak == 1);
+    strip_load(vb, Bm, sbn, sbk, n0, N, k0, Kd, sbk == 1);
     if (k0 > 0) __syncthreads();  // the previous strip's LDS reads are done
     strip_store(As, va, sak == 1, (klen + 31) / 32);
     strip_store(Bs, vb, sbk == 1, (klen + 31) / 32);
@@ -250,12 +254,13 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int Kd, const float 
     const int64_t gm = m0 + wm * 32 + 8 * (v / 4) + 4 * hf + (v % 4);
     if (gm >= M || gn >= N) continue;
     float x = acc[v];
-    if (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) x += bias[gn];
-    if (EPI == EPI_BIAS_GELU) {
+    if (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU || EPI == EPI_BIAS_SELU) x += bias[gn];
+    if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS_SELU) {
       Z[gm * ldz + gn] = x;
-      x = gelu(x);
+      x = EPI == EPI_BIAS_GELU ? gelu(x) : selu(x);
     }
     if (EPI == EPI_GELU_GRAD) x *= gelu_grad(Z[gm * ldz + gn]);
+    if (EPI == EPI_SELU_GRAD) x *= selu_grad(Z[gm * ldz + gn]);
     C[gm * ldc + gn] = x;
   }
 }
@@ -283,8 +288,9 @@ __global__ __launch_bounds__(256) void k_gemm_wgrad(int M, int N, int Bsz, int k
   for (int k0 = 0; k0 < kd; k0 += kStripK) {
     const int klen = kd - k0 < kStripK ? kd - k0 : kStripK;
     float va[8][8], vb[8][8];
-    strip_load(va, Ag, 1, M, m0, M, k0, kd);
-    strip_load(vb, Bg, 1, N, n0, N, k0, kd);
+    // rows are the fast index of both operands (also when M or N is 1)
+    strip_load(va, Ag, 1, M, m0, M, k0, kd, false);
+    strip_load(vb, Bg, 1, N, n0, N, k0, kd, false);
 #pragma unroll
     for (int c = 0; c < 8; ++c)
 #pragma unroll
@@ -394,10 +400,6 @@ __global__ __launch_bounds__(256) void k_loss(int64_t B, int k, const float *__r
 // Optimizer state on the device, so that a recorded training step can be replayed as is:
 // t = Adam steps taken, cursor = batch index within the epoch, c1/c2 = bias corrections of
 // the next step, 1 - beta1^(t+1) and 1 - beta2^(t+1).
-struct TrainState {
-  int64_t t, cursor;
-  float c1, c2;
-};
 
 __device__ __forceinline__ void train_state_set(TrainState *st, int64_t t) {
   st->t = t;
@@ -934,6 +936,70 @@ static open_status mlp_step(open_mlp *p, int64_t B, const int64_t *rows, const i
   OPEN_LAUNCH(ctx, "mlp_adam", k_adam, dim3(1024), dim3(256), 0, p->np, p->w, p->g, p->am, p->av, lr, p->tstate);
   OPEN_LAUNCH(ctx, "mlp_step_end", k_step_end, dim3(1), dim3(64), 0, p->tstate);
   return mlp_repack(p);
+}
+
+// ---------------------------------------------------------------- shared dense-training entry
+// points (declared in dense.h; the NCF training composes them)
+open_status dense_gemm(open_ctx *ctx, const char *name, int epi, int M, int N, int Kd, const float *A, int64_t sam,
+                       int64_t sak, const float *Bm, int64_t sbn, int64_t sbk, float *C, int64_t ldc, const float *bias,
+                       float *Z, int64_t ldz) {
+  switch (epi) {
+    case EPI_STORE: return gemm<EPI_STORE>(ctx, name, M, N, Kd, A, sam, sak, Bm, sbn, sbk, C, ldc, bias, Z, ldz);
+    case EPI_BIAS: return gemm<EPI_BIAS>(ctx, name, M, N, Kd, A, sam, sak, Bm, sbn, sbk, C, ldc, bias, Z, ldz);
+    case EPI_BIAS_SELU:
+      return gemm<EPI_BIAS_SELU>(ctx, name, M, N, Kd, A, sam, sak, Bm, sbn, sbk, C, ldc, bias, Z, ldz);
+    case EPI_SELU_GRAD:
+      return gemm<EPI_SELU_GRAD>(ctx, name, M, N, Kd, A, sam, sak, Bm, sbn, sbk, C, ldc, bias, Z, ldz);
+    default: return fail(ctx, OPEN_E_INVALID, "unknown GEMM epilogue");
+  }
+}
+
+int64_t dense_wgrad_part_floats(int64_t B, int M, int N) { return wgrad_part_floats(B, M, N); }
+
+open_status dense_wgrad(open_ctx *ctx, const char *name, int M, int N, int64_t B, const float *dY, const float *X,
+                        float *part, float *g_w) {
+  int kc;
+  const int S = wgrad_slices(B, M, N, &kc);
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)S);
+  OPEN_LAUNCH(ctx, name, k_gemm_wgrad, grid, dim3(256), 0, M, N, (int)B, kc, dY, X, part);
+  const int64_t tot = (int64_t)M * N + M;
+  int64_t blocks = (tot + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  OPEN_LAUNCH(ctx, "reduce_slices", k_reduce_slices, dim3((unsigned)blocks), dim3(256), 0, tot, S, part, g_w);
+  return OPEN_OK;
+}
+
+open_status dense_train_state_reset(open_ctx *ctx, TrainState *st) {
+  OPEN_LAUNCH(ctx, "train_state_reset", k_train_state_reset, dim3(1), dim3(64), 0, st);
+  return OPEN_OK;
+}
+
+open_status dense_adam_step(open_ctx *ctx, int64_t np, float *w, const float *g, float *am, float *av, float lr,
+                            TrainState *st) {
+  OPEN_LAUNCH(ctx, "adam", k_adam, dim3(1024), dim3(256), 0, np, w, g, am, av, lr, st);
+  OPEN_LAUNCH(ctx, "step_end", k_step_end, dim3(1), dim3(64), 0, st);
+  return OPEN_OK;
+}
+
+open_status dense_loss_final(open_ctx *ctx, const double *part, int nparts, int64_t total, double *loss_d,
+                             float *loss_f, const TrainState *st, float *loss_steps) {
+  OPEN_LAUNCH(ctx, "loss_final", k_loss_final, dim3(1), dim3(64), 0, part, nparts, total, loss_d, loss_f, st,
+              loss_steps);
+  return OPEN_OK;
+}
+
+open_status dense_shuffle(open_ctx *ctx, int64_t m, uint64_t seed, int64_t epoch, int64_t *perm, TrainState *st) {
+  int h = 1;
+  while (h < 31 && (int64_t(1) << (2 * h)) < m) ++h;
+  const int64_t blocks = (m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096;
+  OPEN_LAUNCH(ctx, "shuffle", k_shuffle, dim3((unsigned)blocks), dim3(256), 0, m, h, seed, epoch, perm, st);
+  return OPEN_OK;
+}
+
+open_status dense_rows_of_step(open_ctx *ctx, const int64_t *perm, int batch, const TrainState *st, int64_t *rows) {
+  OPEN_LAUNCH(ctx, "rows_of_step", k_rows_of_step, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, perm, batch,
+              st, rows);
+  return OPEN_OK;
 }
 
 // Seeded initial weights: every weight and bias of a layer with fan-in f uniform on

@@ -40,6 +40,9 @@ SIGNATURES = {
     "open_perf_predict": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "open_ncf_foldin": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _I32, _F32, _F32, _P,
                                _P, _P]),
+    "open_ncf_num_params": (_I64, [_I64, _I32]),
+    "open_ncf_train": (_I32, [_P, _I64, _I32, _I32, _P, _P, _I32, _F32, _I32, ctypes.c_uint64, _P]),
+    "open_ncf_loss_grad": (_I32, [_P, _I64, _I32, _I32, _P, _P, _P, _I32, _P, _P]),
     "open_refit": (_I32, [_P, _I64, _I64, _I32, _I32, _P, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
     "open_tune_info": (_I32, [_I32, _P, _P, _I32]),
     "open_tune_get": (_I32, [_P, _I32, _P, _I32]),
@@ -468,3 +471,55 @@ class Surrogate:
             self.close()
         except Exception:
             pass
+
+
+NCF_D, NCF_H = 32, 64
+
+
+def ncf_pack(E, S, net):
+    """Flat NCF parameter vector (E, S, W1, b1, W2, b2, w3, b3) as float32 numpy."""
+    import numpy as np
+    parts = [E, S, net["W1"], net["b1"], net["W2"], net["b2"], net["w3"], net["b3"]]
+    return np.concatenate([np.asarray(x, np.float32).reshape(-1) for x in parts])
+
+
+def ncf_unpack(flat, m_off, n):
+    """Views (E, S, {W1, b1, W2, b2, w3, b3}) into a flat NCF parameter vector (numpy or torch)."""
+    d, H = NCF_D, NCF_H
+    shapes = [("E", (m_off, d)), ("S", (n, d)), ("W1", (H, 2 * d)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)),
+              ("w3", (H,)), ("b3", (1,))]
+    out, o = {}, 0
+    for name, shp in shapes:
+        c = 1
+        for x in shp:
+            c *= x
+        out[name] = flat[o:o + c].reshape(shp)
+        o += c
+    E, S = out.pop("E"), out.pop("S")
+    return E, S, out
+
+
+def open_ncf_train(ctx, R, params, apps_per_batch, lr, epochs, seed=0):
+    """Train the NCF model (flat device parameter vector, updated in place) on the dense offline
+    matrix R (device float32, m_off x n); returns the mean batch loss of each epoch."""
+    import numpy as np
+    m_off, n = R.shape
+    hist = np.zeros(max(int(epochs), 1), dtype=np.float32)
+    ctx.check(lib().open_ncf_train(ctx.handle, m_off, n, NCF_D, _dev(R, torch.float32, "R", m_off * n),
+                                   _dev(params, torch.float32, "params", lib().open_ncf_num_params(m_off, n)),
+                                   int(apps_per_batch), float(lr), int(epochs), int(seed),
+                                   hist.ctypes.data_as(ctypes.c_void_p)))
+    return hist[:int(epochs)]
+
+
+def open_ncf_loss_grad(ctx, R, params, apps):
+    """Loss and gradient (numpy float32, the flat packing) of the batch of applications `apps`."""
+    import numpy as np
+    m_off, n = R.shape
+    npar = lib().open_ncf_num_params(m_off, n)
+    g = np.empty(npar, dtype=np.float32)
+    loss = ctypes.c_double()
+    ctx.check(lib().open_ncf_loss_grad(ctx.handle, m_off, n, NCF_D, _dev(R, torch.float32, "R", m_off * n),
+                                       _dev(params, torch.float32, "params", npar), _dev(apps, torch.int64, "apps"),
+                                       int(apps.numel()), ctypes.byref(loss), g.ctypes.data_as(ctypes.c_void_p)))
+    return loss.value, g

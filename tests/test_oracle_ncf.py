@@ -166,3 +166,44 @@ def test_flip_moves_only_the_flipped_evaluation():
     g = (dZ1 @ p["W1"])[:, :32].sum(axis=0)
     assert np.allclose(one, -0.5 * g, rtol=1e-13, atol=1e-16)
     assert not np.allclose(one, ncf.foldin_row(S, vals, p, 1, 0.5, 1e-3), rtol=1e-9, atol=0)
+
+
+def test_training_gradient_central_differences():
+    # the offline training objective's gradient with respect to every parameter (embeddings
+    # of applications and settings, both layers, the output) against central differences on a
+    # small model; a wrong sign, a transposed weight or a dropped term in any part fails
+    from oracle import ncf
+    r = np.random.default_rng(8)
+    m_off, n, d, H = 5, 4, 3, 6
+    E = r.standard_normal((m_off, d))
+    S = r.standard_normal((n, d))
+    p = {"W1": r.standard_normal((H, 2 * d)) * 0.6, "b1": r.standard_normal(H) * 0.3,
+         "W2": r.standard_normal((H, H)) * 0.5, "b2": r.standard_normal(H) * 0.3,
+         "w3": r.standard_normal(H) * 0.5, "b3": np.array([0.4])}
+    R = r.uniform(0.3, 1.0, size=(m_off, n))
+    apps = np.array([3, 0, 4])
+    L, g = ncf.train_loss_and_grads(E, S, p, apps, R)
+    h = 1e-6
+
+    def objective(E_, S_, p_):
+        return ncf.train_loss_and_grads(E_, S_, p_, apps, R)[0]
+
+    for name in ["E", "S", "W1", "b1", "W2", "b2", "w3", "b3"]:
+        base = E if name == "E" else S if name == "S" else p[name]
+        num = np.zeros_like(base)
+        for idx in np.ndindex(base.shape):
+            vals = []
+            for sgn in (1, -1):
+                b2 = base.copy()
+                b2[idx] += sgn * h
+                if name == "E":
+                    vals.append(objective(b2, S, p))
+                elif name == "S":
+                    vals.append(objective(E, b2, p))
+                else:
+                    vals.append(objective(E, S, dict(p, **{name: b2})))
+            num[idx] = (vals[0] - vals[1]) / (2 * h)
+        err = np.abs(num - g[name]).max() / max(np.abs(num).max(), 1e-12)
+        assert err <= 1e-6, (name, err)
+    # applications outside the batch get no gradient
+    assert not g["E"][[1, 2]].any()
