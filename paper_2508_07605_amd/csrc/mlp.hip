@@ -25,13 +25,14 @@ namespace openk {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// float32 -> bfloat16 bits, round to nearest even (NaN stays NaN)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __builtin_bit_cast(uint32_t, f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+// float32 -> bfloat16, round to nearest even (NaN stays NaN): the gfx950 conversion
+// instruction v_cvt_pk_bf16_f32, two values at a time; bf16pack(a, b) has a in the low half
+__device__ __forceinline__ uint32_t bf16pack(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf16x2v));
 }
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
 // erf by Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26 (absolute
@@ -67,7 +68,7 @@ __global__ void k_pack_w1p(const float *__restrict__ W1, int H, int n, uint32_t 
   const int64_t total = (int64_t)H * n, twon = 2 * (int64_t)n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = e / H, h = e % H;
-    W1P[e] = (uint32_t)f2bf(W1[h * twon + j]) | ((uint32_t)f2bf(W1[h * twon + n + j]) << 16);
+    W1P[e] = bf16pack(W1[h * twon + j], W1[h * twon + n + j]);
   }
 }
 
@@ -81,7 +82,7 @@ __global__ void k_pack_w2p(const float *__restrict__ W2, uint4 *__restrict__ W2P
   const float *src = W2 + (int64_t)(64 * w + 32 * cb + i) * 256 + 16 * ks + 8 * g;
   uint32_t pk[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) pk[q] = (uint32_t)f2bf(src[2 * q]) | ((uint32_t)f2bf(src[2 * q + 1]) << 16);
+  for (int q = 0; q < 4; ++q) pk[q] = bf16pack(src[2 * q], src[2 * q + 1]);
   W2P[e] = uint4{pk[0], pk[1], pk[2], pk[3]};
 }
 
@@ -98,19 +99,17 @@ __global__ void k_pack_w3p(const float *__restrict__ W3, int K, uint4 *__restric
   if (o < K) {
     const float *src = W3 + (int64_t)o * 256 + 16 * ks + 8 * g;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) pk[q] = (uint32_t)f2bf(src[2 * q]) | ((uint32_t)f2bf(src[2 * q + 1]) << 16);
+    for (int q = 0; q < 4; ++q) pk[q] = bf16pack(src[2 * q], src[2 * q + 1]);
   }
   W3P[e] = uint4{pk[0], pk[1], pk[2], pk[3]};
 }
 
-// The value r of an observed entry as two bfloat16 parts, r = hi + lo to within 2^-17 |r|, in
-// the pairs (hi, 1) and (lo, 0) that multiply a weight pair (value weight, mask weight).  An
-// entry whose column is outside [0, n) takes the pairs (0, 0), (0, 0): it adds nothing.
-__device__ __forceinline__ void value_pairs(float r, bool valid, uint32_t &p1, uint32_t &p2) {
-  const uint16_t hi = f2bf(r);
-  const uint16_t lo = f2bf(r - bf2f(hi));
-  p1 = valid ? ((uint32_t)hi | (0x3f80u << 16)) : 0u;
-  p2 = valid ? (uint32_t)lo : 0u;
+// The value r of an observed entry as the pair (bf16(r), 1) that multiplies a weight pair
+// (value weight, mask weight): one dot product adds a r + c.  The value is rounded to bfloat16
+// like the weights (relative error at most 2^-9).  An entry whose column is outside [0, n)
+// takes the pair (0, 0): it adds nothing.
+__device__ __forceinline__ uint32_t value_pair(float r, bool valid) {
+  return valid ? (uint32_t)f2bf(r) | (0x3f80u << 16) : 0u;
 }
 
 // The lane's weight pairs of setting j (four units, 16 bytes) from the packed first layer
@@ -120,17 +119,14 @@ __device__ __forceinline__ uint4 w1_pairs(__amdgpu_buffer_rsrc_t rs, int j, int 
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
 }
 
-// z += a r + c for the lane's four units (w: their weight pairs), as two bfloat16 dot products
-// per unit with float32 accumulation: (a, c).(hi, 1), then (a, c).(lo, 0).  Every first-layer
-// evaluation (training and inference) takes exactly these steps in the row's entry order.
-__device__ __forceinline__ void layer1_step(f4 &z, uint4 w, uint32_t p1, uint32_t p2) {
-  const bf16x2 y1 = __builtin_bit_cast(bf16x2, p1), y2 = __builtin_bit_cast(bf16x2, p2);
+// z += a r + c for the lane's four units (w: their weight pairs), one bfloat16 dot product
+// per unit with float32 accumulation.  Every first-layer evaluation (training and inference)
+// takes exactly these steps in the row's entry order.
+__device__ __forceinline__ void layer1_step(f4 &z, uint4 w, uint32_t p) {
+  const bf16x2 y = __builtin_bit_cast(bf16x2, p);
   const uint32_t wq[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    z[q] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, wq[q]), y1, z[q], false);
-    z[q] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, wq[q]), y2, z[q], false);
-  }
+  for (int q = 0; q < 4; ++q) z[q] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, wq[q]), y, z[q], false);
 }
 
 // ---------------------------------------------------------------- sparse first layer
@@ -150,9 +146,7 @@ __global__ __launch_bounds__(256) void k_layer1(int64_t B, const int64_t *__rest
     for (int64_t t = ptr[i]; t < ptr[i + 1]; ++t) {
       const int j = col[t];
       const bool ok = j >= 0 && j < n;
-      uint32_t p1, p2;
-      value_pairs(val[t], ok, p1, p2);
-      layer1_step(z, w1_pairs(rs, ok ? j : -1, lane), p1, p2);
+      layer1_step(z, w1_pairs(rs, ok ? j : -1, lane), value_pair(val[t], ok));
     }
     if (z1) *reinterpret_cast<f4 *>(z1 + b * 256 + 4 * lane) = z;
     f4 hv;
@@ -203,7 +197,7 @@ __device__ __forceinline__ void strip_store(uint16_t *__restrict__ Xs, const flo
     if (c < nch) {
       uint32_t pk[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) pk[e] = (uint32_t)f2bf(v[c][2 * e]) | ((uint32_t)f2bf(v[c][2 * e + 1]) << 16);
+      for (int e = 0; e < 4; ++e) pk[e] = bf16pack(v[c][2 * e], v[c][2 * e + 1]);
       *reinterpret_cast<uint4 *>(Xs + row * kLdk + 32 * c + 8 * kg) = uint4{pk[0], pk[1], pk[2], pk[3]};
     }
   }
@@ -536,6 +530,7 @@ __global__ void k_count_u8(int64_t m, const uint8_t *__restrict__ f, int64_t *__
 constexpr int kIR = 64;       // rows per tile
 constexpr int kHP = 256 + 8;  // LDS pitch of an activation row (bf16)
 constexpr int kCap = 176;     // entries staged per wavefront (three blocks per CU up to rank 32)
+static_assert(kCap % 8 == 0, "a staged chunk is padded to a multiple of eight entries");
 
 __device__ __forceinline__ int64_t readlane_i64(int64_t x, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
@@ -556,12 +551,13 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
   constexpr int PF = 4;               // W2 steps loaded ahead
   __shared__ __attribute__((aligned(16))) uint16_t Hs[kIR * kHP];
   __shared__ float Us[kIR * K];
-  // per wavefront: {column or -1, value pair 1, value pair 2, value bits} of its rows' entries
+  // per wavefront: {column or -1, value pair, value bits, 0} of its rows' entries
   __shared__ uint4 Stg[4][kCap];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i32 = lane & 31, g = lane >> 5;
   const float b2c[2] = {b2[64 * w + i32], b2[64 * w + 32 + i32]};
   const f4 b1v = *reinterpret_cast<const f4 *>(b1 + 4 * lane);
+  const uint2 hb1 = uint2{bf16pack(gelu(b1v[0]), gelu(b1v[1])), bf16pack(gelu(b1v[2]), gelu(b1v[3]))};
   const uint4 *w2w = W2P + (int64_t)(2 * w) * 16 * 64 + lane;  // step (cb, ks) at w2w[(cb*16 + ks)*64]
   const __amdgpu_buffer_rsrc_t rs1 = make_rsrc(W1P, (uint64_t)n * 1024);
   uint4 *stg = Stg[w];
@@ -578,61 +574,74 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
     int cur = 0;                                      // row of the wavefront being accumulated
     int nxt = (int)(readlane_i64(pv, 1) - E0);        // first entry (relative) after it
     f4 z = b1v;
-    auto close_row = [&]() {
-      const uint32_t lo = (uint32_t)f2bf(gelu(z[0])) | ((uint32_t)f2bf(gelu(z[1])) << 16);
-      const uint32_t hi = (uint32_t)f2bf(gelu(z[2])) | ((uint32_t)f2bf(gelu(z[3])) << 16);
-      *reinterpret_cast<uint2 *>(Hs + (16 * w + cur) * kHP + 4 * lane) = uint2{lo, hi};
+    auto advance = [&]() {
       ++cur;
-      z = b1v;
       nxt = cur < 16 ? (int)(readlane_i64(pv, cur + 1) - E0) : INT_MAX;
+    };
+    // closes row cur (GELU, bfloat16 into the tile), then stores every following empty row
+    // ending at or before entry u: rows without entries are GELU(b1)
+    auto close_rows = [&](int u) {
+      *reinterpret_cast<uint2 *>(Hs + (16 * w + cur) * kHP + 4 * lane) =
+          uint2{bf16pack(gelu(z[0]), gelu(z[1])), bf16pack(gelu(z[2]), gelu(z[3]))};
+      z = b1v;
+      advance();
+      while (u >= nxt) {
+        *reinterpret_cast<uint2 *>(Hs + (16 * w + cur) * kHP + 4 * lane) = hb1;
+        advance();
+      }
     };
     for (int cs = 0; cs < nent; cs += kCap) {
       const int clen = nent - cs < kCap ? nent - cs : kCap;
+      const int cpad = (clen + 7) & ~7;  // the chunk padded with entries that add nothing
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();  // the previous chunk's reads of the staging area are done
-      for (int t = lane; t < clen; t += 64) {
-        const int j = col[E0 + cs + t];
-        const float r = val[E0 + cs + t];
-        const bool ok = j >= 0 && j < n;
-        uint32_t p1, p2;
-        value_pairs(r, ok, p1, p2);
-        stg[t] = uint4{(uint32_t)(ok ? j : -1), p1, p2, __builtin_bit_cast(uint32_t, r)};
+      for (int t = lane; t < cpad; t += 64) {
+        uint4 e = uint4{0xffffffffu, 0u, 0u, 0u};
+        if (t < clen) {
+          const int j = col[E0 + cs + t];
+          const float r = val[E0 + cs + t];
+          const bool ok = j >= 0 && j < n;
+          e = uint4{(uint32_t)(ok ? j : -1), value_pair(r, ok), __builtin_bit_cast(uint32_t, r), 0u};
+        }
+        stg[t] = e;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      uint4 wv[8];
-      uint32_t q1[8], q2[8];
-      auto fetch = [&](int u0) {
+      // two register sets of eight entries' weight pairs: one loads while the other is added
+      uint4 wa[8], wb[8];
+      uint32_t qa[8], qb[8];
+      auto fetch = [&](uint4 (&wv)[8], uint32_t (&q)[8], int u0) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const uint4 st = stg[u0 + e < clen ? u0 + e : clen - 1];
-          q1[e] = u0 + e < clen ? st.y : 0u;  // past the chunk: adds nothing, and is not taken
-          q2[e] = u0 + e < clen ? st.z : 0u;
+          const uint4 st = stg[u0 + e];
+          q[e] = st.y;
           wv[e] = w1_pairs(rs1, (int)st.x, lane);
         }
       };
-      fetch(0);
-      for (int u0 = 0; u0 < clen; u0 += 8) {
-        uint4 cw[8];
-        uint32_t c1[8], c2[8];
+      // a padding entry adds exact zeros; a row it closes has ended at or before it
+      auto consume = [&](const uint4 (&wv)[8], const uint32_t (&q)[8], int u0) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          cw[e] = wv[e];
-          c1[e] = q1[e];
-          c2[e] = q2[e];
+          if (cs + u0 + e >= nxt) close_rows(cs + u0 + e);
+          layer1_step(z, wv[e], q[e]);
         }
-        if (u0 + 8 < clen) fetch(u0 + 8);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (u0 + e < clen) {
-            while (cs + u0 + e >= nxt) close_row();
-            layer1_step(z, cw[e], c1[e], c2[e]);
-          }
-        }
+      };
+      fetch(wa, qa, 0);
+      for (int u0 = 0; u0 < cpad; u0 += 16) {
+        if (u0 + 8 < cpad) fetch(wb, qb, u0 + 8);
+        consume(wa, qa, u0);
+        if (u0 + 8 >= cpad) break;
+        if (u0 + 16 < cpad) fetch(wa, qa, u0 + 16);
+        consume(wb, qb, u0 + 8);
       }
     }
-    while (cur < 16) close_row();
+    if (cur < 16) close_rows(INT_MAX - 1);
+    // the lane index through an opaque copy: the per-lane addresses of the later phases are
+    // formed here in each tile instead of being hoisted out of the tile loop (and spilled)
+    int lane_o = lane;
+    asm volatile("" : "+v"(lane_o));
+    const int i32o = lane_o & 31, go = (lane_o >> 5) & 1;
     __syncthreads();
     // ---- second layer: this wavefront's 64 output columns for all kIR rows
     f16 acc[2][2] = {};
@@ -656,7 +665,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
         }
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-          const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32) * kHP + 16 * ks + 8 * g);
+          const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32o) * kHP + 16 * ks + 8 * go);
           acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                               __builtin_bit_cast(bf16x8, bw0), acc[rb][0], 0, 0, 0);
           acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
@@ -671,14 +680,14 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int rr = 32 * rb + 8 * (v / 4) + 4 * g + (v % 4);
-          Hs[rr * kHP + 64 * w + 32 * cb + i32] = f2bf(gelu(acc[rb][cb][v] + b2c[cb]));
+          const int rr = 32 * rb + 8 * (v / 4) + 4 * go + (v % 4);
+          Hs[rr * kHP + 64 * w + 32 * cb + i32o] = f2bf(gelu(acc[rb][cb][v] + b2c[cb]));
         }
     __syncthreads();
     // ---- third layer: tiles (row block, 32 outputs) on the first 2 CB3 wavefronts
     if (w < 2 * CB3) {
       const int rb = w & 1, cb = w >> 1;
-      const int oc = 32 * cb + i32;  // output column supplied / received by this lane
+      const int oc = 32 * cb + i32o;  // output column supplied / received by this lane
       f16 acc3 = {};
       int opq = 0;
       asm volatile("" : "+v"(opq));  // keeps the operand loads in the tile loop
@@ -688,7 +697,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
       for (int ks = 0; ks < 16; ++ks) bw[ks] = w3t[ks * 64];
 #pragma unroll
       for (int ks = 0; ks < 16; ++ks) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32) * kHP + 16 * ks + 8 * g);
+        const uint4 a = *reinterpret_cast<const uint4 *>(Hs + (32 * rb + i32o) * kHP + 16 * ks + 8 * go);
         acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bw[ks]),
                                                       acc3, 0, 0, 0);
       }
@@ -696,7 +705,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
         const float bias = b3[oc];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int rr = 32 * rb + 8 * (v / 4) + 4 * g + (v % 4);
+          const int rr = 32 * rb + 8 * (v / 4) + 4 * go + (v % 4);
           const float x = acc3[v] + bias;
           Us[rr * K + oc] = x;
           if (r0 + rr < m) U[(r0 + rr) * K + oc] = x;
@@ -707,10 +716,10 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
     // ---- observed-entry RMS residual: four lanes per row, K/4 dimensions each
     {
       constexpr int KQ = K / 4;
-      const int lr = 16 * w + (lane >> 2), pq = lane & 3;
+      const int lr = 16 * w + (lane_o >> 2), pq = lane_o & 3;
       const int64_t row = r0 + lr;
       // the row's entries [P_q, P_q+1) from the lanes that loaded them (empty past m)
-      const int q = lane >> 2;
+      const int q = lane_o >> 2;
       const int64_t t0 = (int64_t)(((uint64_t)(uint32_t)__shfl((int)((uint64_t)pv >> 32), q, 64) << 32) |
                                    (uint32_t)__shfl((int)(uint32_t)pv, q, 64));
       const int64_t t1 = (int64_t)(((uint64_t)(uint32_t)__shfl((int)((uint64_t)pv >> 32), q + 1, 64) << 32) |
@@ -737,7 +746,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
           if (staged) {
             const uint4 st = stg[in ? sofs + t : 0];
             jv[e] = in ? (int)st.x : -1;
-            rv[e] = in ? __builtin_bit_cast(float, st.w) : 0.f;
+            rv[e] = in ? __builtin_bit_cast(float, st.z) : 0.f;
           } else {
             jv[e] = in ? col[t0 + t] : -1;
             rv[e] = in ? val[t0 + t] : 0.f;
