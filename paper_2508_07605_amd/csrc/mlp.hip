@@ -562,13 +562,32 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
   const __amdgpu_buffer_rsrc_t rs1 = make_rsrc(W1P, (uint64_t)n * 1024);
   uint4 *stg = Stg[w];
   const int64_t ntiles = (m + kIR - 1) / kIR;
+  // The next tile's row pointers and the first staged chunk of its entries are loaded while
+  // the current tile is in its later phases.  Lane q <= 16 holds P_q, the first entry of row
+  // 16 w + q of the tile (rows past m are empty); lane l holds entries l + 64 i of the chunk.
+  constexpr int PK = (kCap + 63) / 64;
+  auto load_ptrs = [&](int64_t tile) -> int64_t {
+    const int64_t prow = tile * kIR + 16 * w + (lane < 16 ? lane : 16);
+    return tile < ntiles ? ptr[prow < m ? prow : m] : 0;
+  };
+  int pcol[PK];
+  float pval[PK];
+  auto load_chunk0 = [&](int64_t pvn) {
+    const int64_t e0 = readlane_i64(pvn, 0);
+    const int64_t nn = readlane_i64(pvn, 16) - e0;
+#pragma unroll
+    for (int i = 0; i < PK; ++i) {
+      const int t = lane + 64 * i;
+      pcol[i] = t < nn && t < kCap ? col[e0 + t] : -1;
+      pval[i] = t < nn && t < kCap ? val[e0 + t] : 0.f;
+    }
+  };
+  int64_t pv_next = load_ptrs(blockIdx.x);
+  load_chunk0(pv_next);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * kIR;
-    const int64_t rw0 = r0 + 16 * w;
     // ---- first layer (sparse), GELU, bfloat16 into LDS
-    // lane q <= 16 holds P_q, the first entry of row rw0 + q (rows past m are empty)
-    const int64_t prow = rw0 + (lane < 16 ? lane : 16);
-    const int64_t pv = ptr[prow < m ? prow : m];
+    const int64_t pv = pv_next;
     const int64_t E0 = readlane_i64(pv, 0);
     const int nent = (int)(readlane_i64(pv, 16) - E0);  // the wavefront's entries, < 2^31
     int cur = 0;                                      // row of the wavefront being accumulated
@@ -595,15 +614,29 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
       const int cpad = (clen + 7) & ~7;  // the chunk padded with entries that add nothing
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();  // the previous chunk's reads of the staging area are done
-      for (int t = lane; t < cpad; t += 64) {
-        uint4 e = uint4{0xffffffffu, 0u, 0u, 0u};
-        if (t < clen) {
-          const int j = col[E0 + cs + t];
-          const float r = val[E0 + cs + t];
-          const bool ok = j >= 0 && j < n;
-          e = uint4{(uint32_t)(ok ? j : -1), value_pair(r, ok), __builtin_bit_cast(uint32_t, r), 0u};
+      if (cs == 0) {
+#pragma unroll
+        for (int i = 0; i < PK; ++i) {
+          const int t = lane + 64 * i;
+          if (t < cpad) {
+            const int j = pcol[i];
+            const float r = pval[i];
+            const bool ok = t < clen && j >= 0 && j < n;
+            stg[t] = t < clen ? uint4{(uint32_t)(ok ? j : -1), value_pair(r, ok), __builtin_bit_cast(uint32_t, r), 0u}
+                              : uint4{0xffffffffu, 0u, 0u, 0u};
+          }
         }
-        stg[t] = e;
+      } else {
+        for (int t = lane; t < cpad; t += 64) {
+          uint4 e = uint4{0xffffffffu, 0u, 0u, 0u};
+          if (t < clen) {
+            const int j = col[E0 + cs + t];
+            const float r = val[E0 + cs + t];
+            const bool ok = j >= 0 && j < n;
+            e = uint4{(uint32_t)(ok ? j : -1), value_pair(r, ok), __builtin_bit_cast(uint32_t, r), 0u};
+          }
+          stg[t] = e;
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -611,12 +644,17 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
       // two register sets of eight entries' weight pairs: one loads while the other is added
       uint4 wa[8], wb[8];
       uint32_t qa[8], qb[8];
+      // the loads are issued in entry order (scheduling barriers), so that each entry waits
+      // only for its own weights and not for the younger loads of the other set
       auto fetch = [&](uint4 (&wv)[8], uint32_t (&q)[8], int u0) {
+        uint4 st[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) st[e] = stg[u0 + e];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const uint4 st = stg[u0 + e];
-          q[e] = st.y;
-          wv[e] = w1_pairs(rs1, (int)st.x, lane);
+          q[e] = st[e].y;
+          wv[e] = w1_pairs(rs1, (int)st[e].x, lane);
+          __builtin_amdgcn_sched_barrier(0);
         }
       };
       // a padding entry adds exact zeros; a row it closes has ended at or before it
@@ -627,16 +665,20 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
           layer1_step(z, wv[e], q[e]);
         }
       };
+      // Every fetch is unconditional (past the chunk it reloads entries 0..7, which are not
+      // taken): a conditional one would make the waits count as if the other set had not been
+      // issued, and each entry would wait for the younger loads too.
       fetch(wa, qa, 0);
       for (int u0 = 0; u0 < cpad; u0 += 16) {
-        if (u0 + 8 < cpad) fetch(wb, qb, u0 + 8);
+        fetch(wb, qb, u0 + 8 < cpad ? u0 + 8 : 0);
         consume(wa, qa, u0);
         if (u0 + 8 >= cpad) break;
-        if (u0 + 16 < cpad) fetch(wa, qa, u0 + 16);
+        fetch(wa, qa, u0 + 16 < cpad ? u0 + 16 : 0);
         consume(wb, qb, u0 + 8);
       }
     }
     if (cur < 16) close_rows(INT_MAX - 1);
+    pv_next = load_ptrs(tile + gridDim.x);
     // the lane index through an opaque copy: the per-lane addresses of the later phases are
     // formed here in each tile instead of being hoisted out of the tile loop (and spilled)
     int lane_o = lane;
@@ -673,6 +715,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
         }
       }
     }
+    load_chunk0(pv_next);
     __syncthreads();  // every wavefront has read the first layer's tile
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
@@ -716,6 +759,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
     // ---- observed-entry RMS residual: four lanes per row, K/4 dimensions each
     {
       constexpr int KQ = K / 4;
+      constexpr int RQ = K <= 32 ? 8 : 4;  // entries per row in flight
       const int lr = 16 * w + (lane_o >> 2), pq = lane_o & 3;
       const int64_t row = r0 + lr;
       // the row's entries [P_q, P_q+1) from the lanes that loaded them (empty past m)
@@ -734,13 +778,13 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
       float ssq = 0.f;
       const bool staged = nent <= kCap;  // wave-uniform: this row's entries are in stg
       const int sofs = (int)(t0 - E0);
-      for (int t0b = 0; t0b < cmax; t0b += 4) {
-        // four entries in flight: indices and values, then the factor rows, then the dots
-        int jv[4];
-        float rv[4];
-        const float *fv[4];
+      for (int t0b = 0; t0b < cmax; t0b += RQ) {
+        // RQ entries in flight: indices and values, then the factor rows, then the dots
+        int jv[RQ];
+        float rv[RQ];
+        const float *fv[RQ];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < RQ; ++e) {
           const int t = t0b + e;
           const bool in = t < cnt;
           if (staged) {
@@ -754,13 +798,13 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
           const bool okj = jv[e] >= 0 && jv[e] < n;
           fv[e] = F + (int64_t)(okj ? jv[e] : 0) * K + pq * KQ;
         }
-        float fx[4][KQ];
+        float fx[RQ][KQ];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < RQ; ++e)
 #pragma unroll
           for (int a = 0; a < KQ; ++a) fx[e][a] = fv[e][a];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < RQ; ++e) {
           float d = 0.f;
 #pragma unroll
           for (int a = 0; a < KQ; ++a) d = __builtin_fmaf(Us[lr * K + pq * KQ + a], fx[e][a], d);
