@@ -42,12 +42,21 @@ def row_flops(n, k):
     return np.where(n == 0, 0.0, np.where(dual, dual_flops(n, k), primal_flops(n, k)))
 
 
-def kernel_of_counts(n, k):
+def kernel_of_counts(n, k, mode=1):
     """Name of the ridge kernel that solves a row with n observations (matches the library):
-    dual rows of n <= min(k, 32) go to the kernel of padded dimension 4 ceil(n/4), longer rows
-    to the primal kernel."""
+    one launch per class group (mode 1): dual rows of n <= min(k, 32) go to the kernel of
+    padded dimension 4 ceil(n/4), longer rows to the primal kernel; the merged launches of rank
+    32 (mode 0: up to 12, 13-24, from 25 observations; mode 2: up to 12, from 13)."""
     import numpy as np
     n = np.asarray(n)
+    if k == 32 and mode in (0, 2):
+        out = np.full(n.shape, "ridge_k32_d4_d12", dtype=object)
+        if mode == 0:
+            out[n > 12] = "ridge_k32_d16_d24"
+            out[n > 24] = "ridge_k32_d28_up"
+        else:
+            out[n > 12] = "ridge_k32_d16_up"
+        return out
     dmax = min(k, 32)
     d = np.maximum(4, 4 * ((n + 3) // 4))
     names = np.array(["ridge_k%d_d%d" % (k, x) for x in range(0, 33)], dtype=object)
@@ -691,7 +700,7 @@ def main():
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
     counts = rows.counts()
-    tiers = kernel_of_counts(counts, k)
+    tiers = kernel_of_counts(counts, k, variants.get("ridge_k%d_launch" % k, 1))
     flops = row_flops(counts, k)
     kernels = {}
     for name, (tot, launches) in prof.items():
@@ -707,7 +716,7 @@ def main():
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roofline = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": recorded_traffic(dom, variants.get(dom)),
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": recorded_traffic(dom, variants.get(dom, -1)),
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": dom, "kernel_ms": round(dom_ms, 4), "kernel_rows": dom_rows,
         "algorithmic_flops": dom_flops, "algorithmic_bytes": dom_bytes,

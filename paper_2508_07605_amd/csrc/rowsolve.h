@@ -537,6 +537,126 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_wa
   }
 }
 
+// ---------------------------------------------------------------- several classes, one launch
+// A size class inside a merged launch: padded dimension D (k for the primal form), the form,
+// and its classes c_lo..c_hi of the bucketed list.
+template <int D_, bool DUAL_, int CLO_, int CHI_>
+struct SizeClass {
+  static constexpr int D = D_, CLO = CLO_, CHI = CHI_;
+  static constexpr bool DUAL = DUAL_;
+};
+
+template <int P, typename... C>
+__host__ __device__ constexpr int multi_wave_floats() {
+  int m = 0;
+  ((m = wave_lds_floats(P, C::D) > m ? wave_lds_floats(P, C::D) : m), ...);
+  return m;
+}
+
+// Persistent kernel over the rows of several size classes that share one launch shape (P lanes
+// per system, W waves per block, OCC waves per SIMD): the groups of 64 / P systems of the
+// classes, in the order given (the costliest first, so that the cheap ones fill the tail), are
+// one index space that the waves stride through.  Each group is solved exactly as by the
+// class's own kernel.
+template <int K, int P, bool LDSF, int W, int OCC, typename... C>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_waves_per_eu(OCC))) void k_solve_multi(
+    const float *__restrict__ F, int n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+    const float *__restrict__ val, const RowRef *__restrict__ list, const int64_t *__restrict__ cls, float lambda,
+    int weighted, float *__restrict__ X, int32_t *__restrict__ status) {
+  constexpr int NC = sizeof...(C);
+  constexpr int SYS = 64 / P;
+  constexpr int WL = multi_wave_floats<P, C...>();
+  constexpr int FL = LDSF ? factor_lds_bytes<K>() / 4 : 4;
+  __shared__ __attribute__((aligned(16))) float lds_all[W * WL + FL];
+  // per class: first list slot, rows, and the first group of the merged index space
+  int64_t cs[NC], cc[NC], g1[NC];
+  {
+    int i = 0;
+    int64_t acc = 0;
+    ((cs[i] = cls[2 * C::CLO], cc[i] = cls[2 * C::CHI] + cls[2 * C::CHI + 1] - cs[i], acc += (cc[i] + SYS - 1) / SYS,
+      g1[i] = acc, ++i),
+     ...);
+  }
+  const int64_t total = g1[NC - 1];  // groups of all classes
+  const int64_t nw = (int64_t)gridDim.x * W;
+  (void)ptr;
+  const int64_t g0 = (int64_t)blockIdx.x * W + (threadIdx.x >> 6);
+  if ((int64_t)blockIdx.x * W >= total) return;  // block has no work (uniform)
+  FRows<K, LDSF> Fr;
+  if constexpr (LDSF) {
+    constexpr int PS = K + 4, CH = K / 4, SL = CH + 1;
+    float *fl = lds_all + W * WL;
+    const int slots = n * SL;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int base = w * 64; base < slots; base += W * 64) {
+      const int e = base + lane < slots ? base + lane : slots - 2;  // slots - 2: last data chunk
+      const int jj = e / SL, cc2 = e % SL;
+      __builtin_amdgcn_global_load_lds(F + (int64_t)jj * K + 4 * (cc2 < CH ? cc2 : 0),
+                                       (__attribute__((address_space(3))) void *)(fl + PS + 4 * base), 16, 0, 0);
+    }
+    if (threadIdx.x < PS) fl[threadIdx.x] = 0.f;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    Fr.lds = fl + PS;
+  } else {
+    Fr.rs = make_rsrc(F, (uint64_t)n * K * sizeof(float));
+  }
+  float *wl = lds_all + (threadIdx.x >> 6) * WL;
+  const int sme = (threadIdx.x & 63) / P;
+  // The wave takes the merged groups g = g0 (mod nw) in increasing order: one loop per class,
+  // over the class's own groups, so that each loop holds only its class's registers.
+  int ci = 0;
+  (
+      [&] {
+        const int i = ci++;
+        const int64_t gb = i ? g1[i - 1] : 0;  // first merged group of the class
+        const int64_t ng = g1[i] - gb;
+        int64_t gl = (g0 - gb) % nw;           // the wave's first group of the class
+        if (gl < 0) gl += nw;
+        auto fetch = [&](int64_t q) -> RowRef {
+          const int64_t sl = q * SYS + sme;
+          return (q < ng && sl < cc[i]) ? list[cs[i] + sl] : RowRef{-1, 0, 0};
+        };
+        RowRef cur = fetch(gl);
+        for (int64_t q = gl; q < ng; q += nw) {
+          const RowRef nxt = fetch(q + nw);  // next group's records load while this group computes
+          solve_group<P, C::D, K, C::DUAL, LDSF, (OCC == 1 || C::D <= 12), false>(Fr, n, cur, idx, val, lambda,
+                                                                                  weighted, X, status, wl);
+          cur = nxt;
+        }
+      }(),
+      ...);
+}
+
+template <int K, int P, int W, int OCC, typename... C>
+open_status launch_multi(const char *name, open_ctx *ctx, const float *F, int n, const int64_t *ptr,
+                         const int32_t *idx, const float *val, float lambda, int weighted, const RowRef *list,
+                         const int64_t *cls, float *X, int32_t *status, int64_t m) {
+  const int64_t groups = (m + 64 / P - 1) / (64 / P) + (int64_t)sizeof...(C);
+  int64_t blocks = (groups + W - 1) / W;
+  constexpr int waves_b = W * multi_wave_floats<P, C...>() * 4;
+  constexpr int flb = factor_lds_bytes<K>();
+  constexpr bool fl_fits = waves_b + flb <= kLdsBytes;
+  static_assert(waves_b + 16 <= kLdsBytes, "per-wave buffers exceed LDS");
+  const bool fl = fl_fits && n <= kFactorLdsRows;
+  const int lds_cu = kLdsBytes / (waves_b + (fl ? flb : 16));
+  const int reg_cu = 4 * OCC / W;
+  int per_cu = lds_cu < reg_cu ? lds_cu : reg_cu;
+  const int64_t cap = (int64_t)ctx->num_cu * (per_cu < 1 ? 1 : per_cu);
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  if constexpr (fl_fits) {
+    if (fl) {
+      OPEN_LAUNCH(ctx, name, (k_solve_multi<K, P, true, W, OCC, C...>), dim3((unsigned)blocks), dim3(64 * W), 0, F, n,
+                  ptr, idx, val, list, cls, lambda, weighted, X, status);
+      return OPEN_OK;
+    }
+  }
+  OPEN_LAUNCH(ctx, name, (k_solve_multi<K, P, false, W, OCC, C...>), dim3((unsigned)blocks), dim3(64 * W), 0, F, n,
+              ptr, idx, val, list, cls, lambda, weighted, X, status);
+  return OPEN_OK;
+}
+
 // Launch the kernel of one size class with a persistent grid sized for m rows: blocks of W
 // waves (sharing one LDS copy of the factors), as many per CU as LDS and the register
 // budget of OCC waves per SIMD allow.
@@ -609,6 +729,9 @@ struct ClassGroup {
 const ClassGroup *class_groups(int k, int *count);
 
 #define OPEN_GROUP(NAME) open_status NAME(int choice, OPEN_TIER_ARGS)
+// The rank-32 pass in merged launches (mode 0: three, mode 2: two), selected by the
+// launch-mode entry of the rank's tuning table (mode 1: one launch per class group).
+open_status rowsolve_k32_merged(int mode, OPEN_TIER_ARGS);
 OPEN_GROUP(g_k8_d4);
 OPEN_GROUP(g_k8_d8);
 OPEN_GROUP(g_k8_primal);

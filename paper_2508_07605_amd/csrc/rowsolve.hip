@@ -31,6 +31,9 @@ const ClassGroup *class_groups(int k, int *count) {
       {"ridge_k32_d28", 7, 7, 2, g_k32_d28},
       {"ridge_k32_d32", 8, 8, 2, g_k32_d32},
       {"ridge_k32_primal", 9, 15, 2, g_k32_primal},
+      // launch mode of the whole pass: 0 = three merged launches, 1 = one launch per group
+      // above, 2 = two merged launches
+      {"ridge_k32_launch", 0, 15, 3, nullptr},
   };
   static const ClassGroup g64[] = {
       {"ridge_k64_d4", 0, 1, 2, g_k64_d4},
@@ -54,6 +57,12 @@ const ClassGroup *class_groups(int k, int *count) {
 
 int rank_index(int k) { return k == 8 ? 0 : k == 16 ? 1 : k == 32 ? 2 : k == 64 ? 3 : -1; }
 
+// The launch mode of the rank: its last table entry when that is a group without a kernel,
+// else 1 (one launch per class group).
+static int launch_mode(const open_ctx *ctx, int k, const ClassGroup *g, int ng) {
+  return (k == 32 && ng > 0 && !g[ng - 1].fn) ? ctx->tune[rank_index(k)][ng - 1] : 1;
+}
+
 open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const int64_t *ptr, const int32_t *idx,
                             const float *val, float lambda, int weighted, const RowRef *list, const int64_t *cls,
                             float *X, int32_t *status, int64_t m) {
@@ -61,7 +70,10 @@ open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const i
   const ClassGroup *g = class_groups(k, &ng);
   if (!g) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
   const int ri = rank_index(k);
+  const int mode = launch_mode(ctx, k, g, ng);
+  if (mode != 1) return rowsolve_k32_merged(mode, OPEN_TIER_PASS, X, status, m);
   for (int i = 0; i < ng; ++i) {
+    if (!g[i].fn) continue;
     open_status st = g[i].fn(ctx->tune[ri][i], OPEN_TIER_PASS, X, status, m);
     if (st) return st;
   }
@@ -96,7 +108,7 @@ open_status rowsolve_autotune(open_ctx *ctx, const float *F, int n, int k, const
   for (int i = 0; i < ng && st == OPEN_OK; ++i) {
     if (ms_out)
       for (int v = 0; v < kMaxVariants; ++v) ms_out[i * kMaxVariants + v] = -1.0;
-    if (rows[i] == 0) continue;
+    if (rows[i] == 0 || !g[i].fn) continue;
     int best = ctx->tune[ri][i];
     double best_ms = 0.0;
     for (int v = 0; v < g[i].nvar && v < kMaxVariants && st == OPEN_OK; ++v) {
@@ -118,6 +130,33 @@ open_status rowsolve_autotune(open_ctx *ctx, const float *F, int n, int k, const
       }
     }
     if (st == OPEN_OK) ctx->tune[ri][i] = (int8_t)best;
+  }
+  // the launch mode: the whole pass in each mode, with the variants just chosen
+  if (st == OPEN_OK && ng > 0 && !g[ng - 1].fn) {
+    const int li = ng - 1;
+    int best = 0;
+    double best_ms = 0.0;
+    for (int v = 0; v < g[li].nvar && v < kMaxVariants && st == OPEN_OK; ++v) {
+      ctx->tune[ri][li] = (int8_t)v;
+      if ((st = rowsolve_launch(ctx, F, n, k, ptr, idx, val, lambda, weighted, list, cls, X, status, m))) break;
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) st = fail(ctx, OPEN_E_DEVICE, "hipEventRecord failed");
+      for (int r = 0; r < reps && st == OPEN_OK; ++r)
+        st = rowsolve_launch(ctx, F, n, k, ptr, idx, val, lambda, weighted, list, cls, X, status, m);
+      if (st) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(ctx, OPEN_E_DEVICE, "event timing failed");
+        break;
+      }
+      const double per = (double)ms / reps;
+      if (ms_out) ms_out[li * kMaxVariants + v] = per;
+      if (v == 0 || per < best_ms) {
+        best_ms = per;
+        best = v;
+      }
+    }
+    ctx->tune[ri][li] = (int8_t)best;
   }
   ctx->prof_on = prof;
   (void)hipEventDestroy(e0);

@@ -168,14 +168,23 @@ def test_every_kernel_variant(ctx, k, n, maxc):
     rp, col, val = csr_from_counts(r, counts, n)
     V = (r.normal(size=(n, k)) * 0.3).astype(np.float32)
     ref, ref_st = oracle.ridge_rows(rp, col, val, V, 0.05, True)
+    # a rank's launch-mode entry (last, named *_launch) selects one launch per class group
+    # (mode 1, where the variants apply) or the merged launches (the other modes)
+    launch = [i for i, (name, _) in enumerate(groups) if name.endswith("_launch")]
     default = ctx.tune_get(k)
     try:
-        for v in range(max(nv for _, nv in groups)):
-            ctx.tune_set(k, [min(v, nv - 1) for _, nv in groups])
+        cases = [(v, 1) for v in range(max(nv for _, nv in groups))]
+        if launch:
+            cases += [(0, mode) for mode in range(groups[launch[0]][1]) if mode != 1]
+        for v, mode in cases:
+            choice = [min(v, nv - 1) for _, nv in groups]
+            for i in launch:
+                choice[i] = mode
+            ctx.tune_set(k, choice)
             U, st = run_gpu(ctx, V, rp, col, val, 0.05)
             assert np.array_equal(st, ref_st)
             e = rel_err(U, ref)[counts > 0]
-            report("variant %d k%d n%d" % (v, k, n), e)
+            report("variant %d launch mode %d k%d n%d" % (v, mode, k, n), e)
             assert e.max() <= TOL
     finally:
         ctx.tune_set(k, default)
