@@ -35,27 +35,38 @@ __device__ __forceinline__ uint32_t bf16pack(float a, float b) {
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
-// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26 (absolute
-// error below 1.5e-7, under the float32 rounding of the activations):
-//   erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x),  x >= 0
-// and erf(-x) = -erf(x).  One reciprocal and one exponential instead of the library's erff.
-__device__ __forceinline__ float erf_as(float x) {
-  const float ax = __builtin_fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.0f));
-  float q = __builtin_fmaf(t, 1.061405429f, -1.453152027f);
-  q = __builtin_fmaf(t, q, 1.421413741f);
-  q = __builtin_fmaf(t, q, -0.284496736f);
-  q = __builtin_fmaf(t, q, 0.254829592f);
-  const float e = __expf(-ax * ax);
-  return __builtin_copysignf(__builtin_fmaf(-t * q, e, 1.0f), x);
+// GELU(z) = z Phi(z) (the erf form), with Phi(z) evaluated as the logistic function of an odd
+// polynomial, Phi(z) ~ 1 / (1 + exp(-(a z + b z^3 + c z^5))), whose three coefficients were
+// fitted to minimise the largest error of GELU over the real line (a = 1.5950157,
+// b = 0.07401132, c = -7.030379e-4; the polynomial is taken at z clamped to [-10, 10], where
+// it is increasing; GELU is taken as 0 below -10).  Largest absolute error of GELU: 2.5e-5,
+// below the bfloat16 rounding of the activations that follows.  One exponential, one
+// reciprocal and eight other instructions.
+// The constants below are -log2(e) times the coefficients (the exponential is exp2).
+constexpr float kGeluC0 = -2.301121234893799f, kGeluC1 = -0.10677576065063477f, kGeluC2 = 0.0010142693063244224f;
+__device__ __forceinline__ float gelu_t(float z) {
+  const float zc = __builtin_amdgcn_fmed3f(z, -10.0f, 10.0f);
+  const float z2 = zc * zc;
+  return zc * __builtin_fmaf(z2, __builtin_fmaf(z2, kGeluC2, kGeluC1), kGeluC0);
 }
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z) {
+  const float v = z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(gelu_t(z)));
+  return z < -10.0f ? 0.0f : v;  // below -10 the clamped polynomial would leave z 9e-13
+}
 // SELU (Klambauer et al. 2017) and its derivative (the right-hand value at 0 is not taken: z > 0)
 constexpr float kSeluA = 1.6732632423543772f, kSeluL = 1.0507009873554805f;
 __device__ __forceinline__ float selu(float z) { return z > 0.f ? kSeluL * z : kSeluL * kSeluA * (__expf(z) - 1.f); }
 __device__ __forceinline__ float selu_grad(float z) { return z > 0.f ? kSeluL : kSeluL * kSeluA * __expf(z); }
+// derivative of the GELU above: s + z s'(z), s = 1 / (1 + e), e = 2^t(z),
+// s' = -s^2 e ln2 t'(z), t' = C0 + 3 C1 z^2 + 5 C2 z^4 (0 where z is clamped)
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  const float e = __builtin_amdgcn_exp2f(gelu_t(z));
+  const float sg = __builtin_amdgcn_rcpf(1.0f + e);
+  const float z2 = z * z;
+  const float tp = __builtin_fabsf(z) < 10.0f
+                       ? __builtin_fmaf(z2, __builtin_fmaf(z2, 5.0f * kGeluC2, 3.0f * kGeluC1), kGeluC0)
+                       : 0.0f;
+  return sg - z * sg * sg * e * 0.69314718055994531f * tp;
 }
 
 // ---------------------------------------------------------------- bfloat16 weight copies
@@ -661,7 +672,9 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
       auto consume = [&](const uint4 (&wv)[8], const uint32_t (&q)[8], int u0) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          if (cs + u0 + e >= nxt) close_rows(cs + u0 + e);
+          // rows end at one entry in ~14: the close is laid out of line, so that the common
+          // path falls through instead of taking a branch per entry
+          if (__builtin_expect(cs + u0 + e >= nxt, 0)) close_rows(cs + u0 + e);
           layer1_step(z, wv[e], q[e]);
         }
       };
