@@ -46,16 +46,13 @@ def kernel_of_counts(n, k, mode=1):
     """Name of the ridge kernel that solves a row with n observations (matches the library):
     one launch per class group (mode 1): dual rows of n <= min(k, 32) go to the kernel of
     padded dimension 4 ceil(n/4), longer rows to the primal kernel; the merged launches of rank
-    32 (mode 0: up to 12, 13-24, from 25 observations; mode 2: up to 12, from 13)."""
+    32 (mode 0): up to 12, 13-24, from 25 observations."""
     import numpy as np
     n = np.asarray(n)
-    if k == 32 and mode in (0, 2):
+    if k == 32 and mode == 0:
         out = np.full(n.shape, "ridge_k32_d4_d12", dtype=object)
-        if mode == 0:
-            out[n > 12] = "ridge_k32_d16_d24"
-            out[n > 24] = "ridge_k32_d28_up"
-        else:
-            out[n > 12] = "ridge_k32_d16_up"
+        out[n > 12] = "ridge_k32_d16_d24"
+        out[n > 24] = "ridge_k32_d28_up"
         return out
     dmax = min(k, 32)
     d = np.maximum(4, 4 * ((n + 3) // 4))

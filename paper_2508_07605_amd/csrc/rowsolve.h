@@ -729,9 +729,9 @@ struct ClassGroup {
 const ClassGroup *class_groups(int k, int *count);
 
 #define OPEN_GROUP(NAME) open_status NAME(int choice, OPEN_TIER_ARGS)
-// The rank-32 pass in merged launches (mode 0: three, mode 2: two), selected by the
-// launch-mode entry of the rank's tuning table (mode 1: one launch per class group).
-open_status rowsolve_k32_merged(int mode, OPEN_TIER_ARGS);
+// The rank-32 pass in three merged launches, selected by the launch-mode entry of the rank's
+// tuning table (0: merged, 1: one launch per class group).
+open_status rowsolve_k32_merged(OPEN_TIER_ARGS);
 OPEN_GROUP(g_k8_d4);
 OPEN_GROUP(g_k8_d8);
 OPEN_GROUP(g_k8_primal);

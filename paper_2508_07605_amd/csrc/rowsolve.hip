@@ -31,9 +31,8 @@ const ClassGroup *class_groups(int k, int *count) {
       {"ridge_k32_d28", 7, 7, 2, g_k32_d28},
       {"ridge_k32_d32", 8, 8, 2, g_k32_d32},
       {"ridge_k32_primal", 9, 15, 2, g_k32_primal},
-      // launch mode of the whole pass: 0 = three merged launches, 1 = one launch per group
-      // above, 2 = two merged launches
-      {"ridge_k32_launch", 0, 15, 3, nullptr},
+      // launch mode of the whole pass: 0 = three merged launches, 1 = one launch per group above
+      {"ridge_k32_launch", 0, 15, 2, nullptr},
   };
   static const ClassGroup g64[] = {
       {"ridge_k64_d4", 0, 1, 2, g_k64_d4},
@@ -70,8 +69,7 @@ open_status rowsolve_launch(open_ctx *ctx, const float *F, int n, int k, const i
   const ClassGroup *g = class_groups(k, &ng);
   if (!g) return fail(ctx, OPEN_E_UNSUPPORTED, "rank must be 8, 16, 32 or 64");
   const int ri = rank_index(k);
-  const int mode = launch_mode(ctx, k, g, ng);
-  if (mode != 1) return rowsolve_k32_merged(mode, OPEN_TIER_PASS, X, status, m);
+  if (launch_mode(ctx, k, g, ng) == 0) return rowsolve_k32_merged(OPEN_TIER_PASS, X, status, m);
   for (int i = 0; i < ng; ++i) {
     if (!g[i].fn) continue;
     open_status st = g[i].fn(ctx->tune[ri][i], OPEN_TIER_PASS, X, status, m);
