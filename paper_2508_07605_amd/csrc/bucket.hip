@@ -67,12 +67,24 @@ __device__ __forceinline__ void load_wave_rows(WaveRows &r, int64_t m, const int
   }
 }
 
-// per-class count of the wave's rows, class cc held by lane cc
-__device__ __forceinline__ int wave_class_counts(const WaveRows &r, int lane) {
+// the classes that occur among the wave's rows, as a bit set (the same value in every lane)
+__device__ __forceinline__ unsigned wave_classes_present(const WaveRows &r) {
+  unsigned bits = 0;
+#pragma unroll
+  for (int p = 0; p < kPasses; ++p) bits |= r.c[p] >= 0 ? (1u << r.c[p]) : 0u;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) bits |= (unsigned)__shfl_xor((int)bits, off, kWave);
+  return (unsigned)__builtin_amdgcn_readfirstlane((int)bits);
+}
+
+// per-class count of the wave's rows, class cc held by lane cc; one ballot per pass and
+// class present (a fold-in batch has a handful of classes out of 17)
+__device__ __forceinline__ int wave_class_counts(const WaveRows &r, int lane, unsigned present) {
   int mine = 0;
 #pragma unroll
   for (int p = 0; p < kPasses; ++p)
-    for (int cc = 0; cc < kNumClasses; ++cc) {
+    for (unsigned b = present; b; b &= b - 1) {
+      const int cc = __builtin_ctz(b);
       const int n = __popcll(__ballot(r.c[p] == cc));
       mine += lane == cc ? n : 0;
     }
@@ -89,7 +101,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_count(int64_t m, const
   WaveRows r;
   load_wave_rows(r, m, ptr, mask, k, split_min, (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)w * kRowsPerWave,
                  lane);
-  const int mine = wave_class_counts(r, lane);
+  const int mine = wave_class_counts(r, lane, wave_classes_present(r));
   if (lane < kNumClasses) atomicAdd(&h[lane], mine);
   __syncthreads();
   if (threadIdx.x < kNumClasses) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -200,7 +212,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
   const int64_t wbase = (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)w * kRowsPerWave;
   WaveRows r;
   load_wave_rows(r, m, ptr, mask, k, split_min, wbase, lane);
-  const int mine = wave_class_counts(r, lane);
+  const unsigned present = wave_classes_present(r);
+  const int mine = wave_class_counts(r, lane, present);
   if (lane < kNumClasses) wcnt[w][lane] = mine;
   __syncthreads();
   int pos = 0;
@@ -213,7 +226,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
   for (int p = 0; p < kPasses; ++p) {
     const int c = r.c[p];
     int rank = 0, add = 0;
-    for (int cc = 0; cc < kNumClasses; ++cc) {
+    for (unsigned b = present; b; b &= b - 1) {
+      const int cc = __builtin_ctz(b);
       const unsigned long long bm = __ballot(c == cc);
       if (c == cc) rank = __popcll(bm & below);
       if (lane == cc) add = __popcll(bm);

@@ -134,6 +134,12 @@ def test_fallback_limits_and_middle(ctx, data):
     Um, used, rho = Um.cpu().numpy(), used.cpu().numpy().astype(bool), rho.cpu().numpy()
     assert np.array_equal(used, ~(rho <= tau)) and nfm == used.sum()
     assert np.array_equal(Um[used], als[used]) and np.array_equal(Um[~used], fwd[~used])
+    # the kernel's residual is the observed-entry RMS residual of its own output (the network's
+    # rows), against the oracle's evaluation of that definition on the same factors
+    ref_rho = oracle.residual(rows.row_ptr, rows.col, rows.val, fwd.astype(np.float64), V.astype(np.float64))
+    e = np.abs(rho - ref_rho) / np.maximum(ref_rho, 1e-30)
+    print("surrogate residual vs oracle: max rel err %.2e" % e.max())
+    assert e.max() <= 1e-5
     net.close()
 
 
