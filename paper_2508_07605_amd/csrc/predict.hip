@@ -6,7 +6,8 @@
 // stride so the 32 lanes of a half-wave read distinct banks).  The epilogue applies the
 // paper's rule to every element without materialising p:
 //   p_base = p_ib                          (the same MFMA value the scan sees for s = b)
-//   valid  = p > 0  and  1 - p / p_base <= gamma      (float32, correctly rounded division)
+//   valid  = p > 0  and  1 - p / p_base <= gamma      (float32, correctly rounded division; as
+//            the equivalent p >= t with t found once per row, the test being monotone in p)
 //   E      = (c_s + g_s) / p                (float32)
 //   keep the least E, the lowest s on ties  ==  the greatest saving (E_base - E) / E_base
 // Each lane scans its own settings in ascending order; the 32 lanes of a half-wave are then
@@ -19,12 +20,23 @@ namespace openk {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 
+// V block s0 (32 settings x K) as K/8 floats per thread of a 256-thread block: load from global,
+// then store transposed into LDS at stride LD (settings past n read as zero)
 template <int K>
-__device__ __forceinline__ void stage_block(float *Vt, const float *__restrict__ V, int n, int s0) {
+__device__ __forceinline__ void load_block(float (&t)[K / 8], const float *__restrict__ V, int n, int s0) {
+#pragma unroll
+  for (int i = 0; i < K / 8; ++i) {
+    const int e = threadIdx.x + 256 * i, j = e / K, kk = e % K;
+    t[i] = (s0 + j < n) ? V[(int64_t)(s0 + j) * K + kk] : 0.f;
+  }
+}
+template <int K>
+__device__ __forceinline__ void store_block(float *Vt, const float (&t)[K / 8]) {
   constexpr int LD = 33;
-  for (int e = threadIdx.x; e < 32 * K; e += blockDim.x) {
-    const int j = e / K, kk = e % K;
-    Vt[kk * LD + j] = (s0 + j < n) ? V[(int64_t)(s0 + j) * K + kk] : 0.f;
+#pragma unroll
+  for (int i = 0; i < K / 8; ++i) {
+    const int e = threadIdx.x + 256 * i, j = e / K, kk = e % K;
+    Vt[kk * LD + j] = t[i];
   }
 }
 
@@ -37,6 +49,21 @@ __device__ __forceinline__ f16v tile(const float (&a)[K / 2], const float *Vt, i
   return acc;
 }
 
+// The rule's validity test 1 - p / p_base <= gamma (float32, correctly rounded division and
+// subtraction) is monotone in p for p_base > 0: fl(p / p_base) does not decrease as p grows and
+// fl(1 - x) does not increase as x grows.  So it holds exactly for p >= t, t the least float
+// for which it holds, found once per row from the real threshold (1 - gamma) p_base by stepping
+// a few units in the last place (the two roundings move it by about two).
+__device__ __forceinline__ bool loss_ok(float p, float pb, float gamma) { return (1.0f - p / pb) <= gamma; }
+__device__ __forceinline__ float least_valid(float pb, float gamma) {
+  float t = (1.0f - gamma) * pb;
+  if (!(t > 0.f)) return 0.f;  // gamma >= 1: every p > 0 passes (1 - p / p_base < 1 <= gamma)
+  auto step = [](float x, int d) { return __builtin_bit_cast(float, __builtin_bit_cast(int, x) + d); };
+  for (int i = 0; i < 64 && loss_ok(step(t, -1), pb, gamma); ++i) t = step(t, -1);
+  for (int i = 0; i < 64 && !loss_ok(t, pb, gamma); ++i) t = step(t, 1);
+  return t;
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_predict_select(const float *__restrict__ U, int64_t m,
                                                         const float *__restrict__ V, int n,
@@ -46,7 +73,7 @@ __global__ __launch_bounds__(256) void k_predict_select(const float *__restrict_
                                                         float *__restrict__ best_saving,
                                                         int32_t *__restrict__ status) {
   constexpr int H = K / 2, LD = 33;
-  __shared__ float Vt[K * LD];
+  __shared__ float Vt[2][K * LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * 32;
@@ -64,43 +91,63 @@ __global__ __launch_bounds__(256) void k_predict_select(const float *__restrict_
   // rows of this lane's 16 accumulators: 8*(v/4) + 4*h + v%4
   // baseline prediction from the same MFMA tile the scan uses
   const int sb0 = (base / 32) * 32, jb = base - sb0;
-  stage_block<K>(Vt, V, n, sb0);
+  float tb[K / 8];
+  load_block<K>(tb, V, n, sb0);
+  store_block<K>(Vt[1], tb);
+  load_block<K>(tb, V, n, 0);  // the scan's first block
   __syncthreads();
-  float pb[16];
+  float pb[16], thr[16];
   {
-    const f16v acc = tile<K>(a, Vt, r, h);
+    const f16v acc = tile<K>(a, Vt[1], r, h);
 #pragma unroll
     for (int v = 0; v < 16; ++v) pb[v] = __shfl(acc[v], jb + 32 * h, 64);
+  }
+  // per row: valid(p) <=> p_base > 0 and p > 0 and p >= thr
+  unsigned rowok = 0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    rowok |= (pb[v] > 0.f ? 1u : 0u) << v;
+    thr[v] = pb[v] > 0.f ? least_valid(pb[v], gamma) : 0.f;
   }
   float bE[16];
   int bS[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    bE[v] = 0.f;
+    bE[v] = __builtin_inff();
     bS[v] = -1;
   }
-  for (int s0 = 0; s0 < n; s0 += 32) {
-    __syncthreads();
-    stage_block<K>(Vt, V, n, s0);
-    __syncthreads();
-    const f16v acc = tile<K>(a, Vt, r, h);
+  store_block<K>(Vt[0], tb);
+  if (32 < n) load_block<K>(tb, V, n, 32);
+  __syncthreads();
+  // Double-buffered stream of V blocks: block i is read from Vt[i & 1] while block i + 1 goes
+  // into the other buffer and block i + 2 loads into registers; one barrier per block.
+  for (int s0 = 0, i = 0; s0 < n; s0 += 32, ++i) {
+    const f16v acc = tile<K>(a, Vt[i & 1], r, h);
+    if (s0 + 32 < n) store_block<K>(Vt[(i + 1) & 1], tb);
+    if (s0 + 64 < n) load_block<K>(tb, V, n, s0 + 64);
     const int sc = s0 + r;
     const bool colok = sc < n;
-    const float wcol = colok ? cap_c[sc] + cap_g[sc] : 0.f;
+    const int scl = colok ? sc : n - 1;
+    const float wcol = cap_c[scl] + cap_g[scl];
+    if (P) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = row0 + 8 * (v / 4) + 4 * h + (v % 4);
-      const float p = acc[v];
-      if (P && colok && row < m) P[row * n + sc] = p;
-      const bool valid = colok && p > 0.f && pb[v] > 0.f && (1.0f - p / pb[v]) <= gamma;
-      if (valid) {
-        const float E = wcol / p;
-        if (bS[v] < 0 || E < bE[v]) {
-          bE[v] = E;
-          bS[v] = sc;
-        }
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + 8 * (v / 4) + 4 * h + (v % 4);
+        if (colok && row < m) P[row * n + sc] = acc[v];
       }
     }
+    // branch-free: least E = (c_s + g_s) / p among valid settings, the lane's settings in
+    // ascending order, the first on ties
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float p = acc[v];
+      const bool valid = colok && ((rowok >> v) & 1u) && p > 0.f && p >= thr[v];
+      const float E = wcol / p;
+      const bool better = valid && (bS[v] < 0 || E < bE[v]);
+      bE[v] = better ? E : bE[v];
+      bS[v] = better ? sc : bS[v];
+    }
+    __syncthreads();
   }
   // combine the 32 column lanes of each half-wave: least E, then lowest s
 #pragma unroll
