@@ -217,8 +217,11 @@ open_status open_residual(open_ctx *ctx, int64_t m, int32_t n, int32_t k, const 
  * baseline setting `base` = (C_b, G_b), E_base = C_b + G_b; setting s is valid when p_is > 0
  * and 1 - p_is / p_ib <= gamma; its energy bound is E_s = (c_s + g_s) / p_is; the valid
  * setting of least E_s (greatest saving (E_base - E_s) / E_base) wins, the lowest s on ties.
+ * In float32 the validity test is evaluated exactly as written (correctly rounded division);
+ * the least E_s is taken as the greatest p_is * fl(1 / (c_s + g_s)), and the saving from
+ * E_s = fl((c_s + g_s) / p_is) of the winner.
  *   U          device float32[m*k];  V device float32[n*k]
- *   cap_cpu, cap_gpu  device float32[n], watts of setting s
+ *   cap_cpu, cap_gpu  device float32[n], watts of setting s (c_s + g_s finite and positive)
  *   P          device float32[m*n] or NULL (the full prediction is only written when asked)
  *   best_idx   device int32[m]; best_saving device float32[m] or NULL
  *   row_status device int32[m] or NULL (OPEN_ROW_NONPOS_BASE when p_ib <= 0; then

@@ -8,8 +8,9 @@
 //   p_base = p_ib                          (the same MFMA value the scan sees for s = b)
 //   valid  = p > 0  and  1 - p / p_base <= gamma      (float32, correctly rounded division; as
 //            the equivalent p >= t with t found once per row, the test being monotone in p)
-//   E      = (c_s + g_s) / p                (float32)
-//   keep the least E, the lowest s on ties  ==  the greatest saving (E_base - E) / E_base
+//   E      = (c_s + g_s) / p: the least E is the greatest key p * iw_s, iw_s = 1 / (c_s + g_s)
+//            (float32, one division per setting instead of one per element); the lowest s on
+//            ties; the saving (E_base - E) / E_base with E = (c_s + g_s) / p of the pick
 // Each lane scans its own settings in ascending order; the 32 lanes of a half-wave are then
 // combined by (E, s) in a butterfly.  The full prediction P is written only when asked.
 #include <math.h>
@@ -57,7 +58,7 @@ __device__ __forceinline__ f16v tile(const float (&a)[K / 2], const float *Vt, i
 __device__ __forceinline__ bool loss_ok(float p, float pb, float gamma) { return (1.0f - p / pb) <= gamma; }
 __device__ __forceinline__ float least_valid(float pb, float gamma) {
   float t = (1.0f - gamma) * pb;
-  if (!(t > 0.f)) return 0.f;  // gamma >= 1: every p > 0 passes (1 - p / p_base < 1 <= gamma)
+  if (!(t > 0.f)) return __builtin_bit_cast(float, 1);  // gamma >= 1: every p > 0 passes
   auto step = [](float x, int d) { return __builtin_bit_cast(float, __builtin_bit_cast(int, x) + d); };
   for (int i = 0; i < 64 && loss_ok(step(t, -1), pb, gamma); ++i) t = step(t, -1);
   for (int i = 0; i < 64 && !loss_ok(t, pb, gamma); ++i) t = step(t, 1);
@@ -102,18 +103,15 @@ __global__ __launch_bounds__(256) void k_predict_select(const float *__restrict_
 #pragma unroll
     for (int v = 0; v < 16; ++v) pb[v] = __shfl(acc[v], jb + 32 * h, 64);
   }
-  // per row: valid(p) <=> p_base > 0 and p > 0 and p >= thr
-  unsigned rowok = 0;
+  // per row: valid(p) <=> p >= thr (thr > 0, so p > 0 follows; NaN when p_base <= 0: never)
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    rowok |= (pb[v] > 0.f ? 1u : 0u) << v;
-    thr[v] = pb[v] > 0.f ? least_valid(pb[v], gamma) : 0.f;
-  }
-  float bE[16];
+  for (int v = 0; v < 16; ++v) thr[v] = pb[v] > 0.f ? least_valid(pb[v], gamma) : __builtin_nanf("");
+  float bK[16], bP[16];  // the best key and its prediction
   int bS[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    bE[v] = __builtin_inff();
+    bK[v] = -__builtin_inff();
+    bP[v] = 0.f;
     bS[v] = -1;
   }
   store_block<K>(Vt[0], tb);
@@ -128,7 +126,8 @@ __global__ __launch_bounds__(256) void k_predict_select(const float *__restrict_
     const int sc = s0 + r;
     const bool colok = sc < n;
     const int scl = colok ? sc : n - 1;
-    const float wcol = cap_c[scl] + cap_g[scl];
+    // past the last setting the key is NaN and never taken
+    const float iw = colok ? 1.0f / (cap_c[scl] + cap_g[scl]) : __builtin_nanf("");
     if (P) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -136,28 +135,30 @@ __global__ __launch_bounds__(256) void k_predict_select(const float *__restrict_
         if (colok && row < m) P[row * n + sc] = acc[v];
       }
     }
-    // branch-free: least E = (c_s + g_s) / p among valid settings, the lane's settings in
-    // ascending order, the first on ties
+    // branch-free: greatest key p * iw among valid settings, the lane's settings in ascending
+    // order, the first on ties
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float p = acc[v];
-      const bool valid = colok && ((rowok >> v) & 1u) && p > 0.f && p >= thr[v];
-      const float E = wcol / p;
-      const bool better = valid && (bS[v] < 0 || E < bE[v]);
-      bE[v] = better ? E : bE[v];
+      const float key = p * iw;
+      const bool better = p >= thr[v] && key > bK[v];
+      bK[v] = better ? key : bK[v];
+      bP[v] = better ? p : bP[v];
       bS[v] = better ? sc : bS[v];
     }
     __syncthreads();
   }
-  // combine the 32 column lanes of each half-wave: least E, then lowest s
+  // combine the 32 column lanes of each half-wave: greatest key, then lowest s
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
 #pragma unroll
     for (int off = 16; off >= 1; off >>= 1) {
-      const float E2 = __shfl_xor(bE[v], off, 64);
+      const float K2 = __shfl_xor(bK[v], off, 64);
+      const float P2 = __shfl_xor(bP[v], off, 64);
       const int S2 = __shfl_xor(bS[v], off, 64);
-      const bool take = S2 >= 0 && (bS[v] < 0 || E2 < bE[v] || (E2 == bE[v] && S2 < bS[v]));
-      bE[v] = take ? E2 : bE[v];
+      const bool take = S2 >= 0 && (bS[v] < 0 || K2 > bK[v] || (K2 == bK[v] && S2 < bS[v]));
+      bK[v] = take ? K2 : bK[v];
+      bP[v] = take ? P2 : bP[v];
       bS[v] = take ? S2 : bS[v];
     }
   }
@@ -169,7 +170,11 @@ __global__ __launch_bounds__(256) void k_predict_select(const float *__restrict_
       if (row >= m) continue;
       const bool okb = pb[v] > 0.f && bS[v] >= 0;
       best_idx[row] = okb ? bS[v] : base;
-      if (best_saving) best_saving[row] = okb ? (ebase - bE[v]) / ebase : 0.f;
+      if (best_saving) {
+        const int sb = okb ? bS[v] : base;
+        const float E = (cap_c[sb] + cap_g[sb]) / bP[v];
+        best_saving[row] = okb ? (ebase - E) / ebase : 0.f;
+      }
       if (status) status[row] = okb ? OPEN_ROW_OK : OPEN_ROW_NONPOS_BASE;
     }
   }

@@ -26,18 +26,22 @@ def dev(a):
 
 
 def mirror_f32(P, cap_c, cap_g, base, gamma):
-    """Alg. 2 on float32 predictions with float32 operations (correctly rounded division)."""
+    """Alg. 2 on float32 predictions with the kernel's float32 operations: validity by the
+    correctly rounded 1 - p / p_base <= gamma; the least E = w / p as the greatest key
+    p * fl(1 / w) (first index on ties); the saving from E = fl(w / p) of the pick."""
     P = P.astype(np.float32)
     w = (cap_c.astype(np.float32) + cap_g.astype(np.float32)).astype(np.float32)
+    iw = (np.float32(1) / w).astype(np.float32)
     pb = P[:, base:base + 1]
     with np.errstate(divide="ignore", invalid="ignore"):
         loss = np.float32(1.0) - (P / pb).astype(np.float32)
         valid = (P > 0) & (pb > 0) & (loss.astype(np.float32) <= np.float32(gamma))
-        E = np.where(valid, (w[None, :] / P).astype(np.float32), np.float32(np.inf))
-    best = np.argmin(E, axis=1).astype(np.int32)  # first index of the minimum
+        key = np.where(valid, (P * iw[None, :]).astype(np.float32), np.float32(-np.inf))
+    best = np.argmax(key, axis=1).astype(np.int32)  # first index of the maximum
     ok = (pb[:, 0] > 0) & valid.any(axis=1)
     ebase = np.float32(cap_c[base]) + np.float32(cap_g[base])
-    Ebest = E[np.arange(len(P)), best]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Ebest = (w[best] / P[np.arange(len(P)), best]).astype(np.float32)
     sav = np.where(ok, ((ebase - Ebest) / ebase).astype(np.float32), np.float32(0))
     best = np.where(ok, best, base)
     return best, sav.astype(np.float32), ok
