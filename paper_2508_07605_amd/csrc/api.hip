@@ -20,7 +20,7 @@ namespace openk {
 constexpr int64_t kNoAllocMaxRows = int64_t(1) << 20;
 constexpr size_t kScrList = 0;
 constexpr size_t kScrHist = kScrList + sizeof(RowRef) * (size_t)kNoAllocMaxRows;
-constexpr size_t kScrCls = kScrHist + ((sizeof(int32_t) * (size_t)kNumClasses * (size_t)(kNoAllocMaxRows / 4096) + 255) &
+constexpr size_t kScrCls = kScrHist + ((sizeof(int32_t) * (size_t)kNumClasses * (size_t)(kNoAllocMaxRows / kBucketRowsPerBlock) + 255) &
                                        ~(size_t)255);
 constexpr size_t kScrBytes = kScrCls + sizeof(int64_t) * 2 * kNumClasses;
 static __device__ __align__(256) unsigned char scratch[kScrBytes];

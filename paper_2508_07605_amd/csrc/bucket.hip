@@ -16,12 +16,12 @@ __global__ void k_fill_i32(int *p, int64_t n, int v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-constexpr int kRowsPerBlock = 4096;
+constexpr int kRowsPerBlock = kBucketRowsPerBlock;
 constexpr int kBucketThreads = 512;
 constexpr int kRowsPerWave = kRowsPerBlock / (kBucketThreads / kWave);  // contiguous rows of one wave
 // Up to this many blocks the place kernel derives its own offsets from the raw histogram
 // (each block reads kNumClasses * nblk counts from L2), so no scan launch is needed.
-constexpr int kSelfScanMaxBlocks = 256;
+constexpr int kSelfScanMaxBlocks = 512;
 
 __device__ __forceinline__ int row_class(int64_t cnt, int k, int64_t split_min) {
   if (cnt <= 0) return 0;

@@ -217,6 +217,8 @@ open_status bucket_rows(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k,
 open_status bucket_rows_into(open_ctx *ctx, int64_t m, const int64_t *row_ptr, int k, int32_t *hist, RowRef *list,
                              int64_t *cls, int64_t split_min, const uint8_t *mask = nullptr);
 int64_t bucket_hist_ints(int64_t m);
+// rows per block of the bucketing kernels (the per-block class counts are kNumClasses ints)
+constexpr int kBucketRowsPerBlock = 2048;
 // Column view on the device (stable counting sort); entries with a column outside [0, n) are dropped.
 open_status csr_to_csc_dev(open_ctx *ctx, int64_t m, int n, const int64_t *row_ptr, const int32_t *col,
                            const float *val, int64_t *col_ptr, int32_t *row_idx, float *cval);
