@@ -565,7 +565,7 @@ __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *
   // per wavefront: {column or -1, value pair, value bits, 0} of its rows' entries
   __shared__ uint4 Stg[4][kCap];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i32 = lane & 31, g = lane >> 5;
+  const int i32 = lane & 31;
   const float b2c[2] = {b2[64 * w + i32], b2[64 * w + 32 + i32]};
   const f4 b1v = *reinterpret_cast<const f4 *>(b1 + 4 * lane);
   const uint2 hb1 = uint2{bf16pack(gelu(b1v[0]), gelu(b1v[1])), bf16pack(gelu(b1v[2]), gelu(b1v[3]))};

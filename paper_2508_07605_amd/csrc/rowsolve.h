@@ -18,12 +18,14 @@
 //          dual form, the observation for the primal form.  FP32 inputs and accumulation.
 //          The instruction's output puts column 4J+q of tile (I, J) in lane q of the quad.
 //   Layout The P lanes of a system own its columns interleaved: lane pi owns c = P m + pi and
-//          keeps rows P m .. D-1 of them in registers.  For P = 4 that is exactly the MFMA
-//          output; for P < 4 the lower triangle passes through a per-wave LDS buffer.
+//          keeps rows P m .. D-1 of them in registers; for P < 4 the lower triangle passes
+//          through a per-wave LDS buffer.  With P = 4 the lanes own rows instead (lane pi: row
+//          4I + pi, columns 0 .. 4I + 3), which the MFMA writes directly when its operands are
+//          swapped; the blocked elimination keeps the column layout.
 //   Solve  Right-looking symmetric Gaussian elimination (LDL^T, no pivoting: the systems are
-//          SPD) with the forward substitution fused in, then a column-oriented back
-//          substitution.  Pivot columns move between the P lanes by DPP quad_perm; with
-//          P = 1 no data moves at all.
+//          SPD) with the forward substitution fused in, then the back substitution (column-
+//          oriented; with owned rows, a sum per lane and a quad reduction per unknown).  Pivot
+//          columns move between the P lanes by DPP quad_perm; with P = 1 no data moves at all.
 //   Output dual: each lane forms K/P outputs of u = F_O^T a from its system's factor rows;
 //          primal: the solution is u itself.
 // Padded rows of a dual system (i >= n_i) have zero factors, unit diagonal and zero rhs:
@@ -103,6 +105,10 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
   constexpr int E = D + 1;            // LDS pitch of a system's index/value lists
   static_assert(D % 4 == 0 && D % P == 0, "shape");
   static_assert(DUAL || D == K, "primal systems are k x k");
+  // Four lanes per system (not blocked) own rows instead of columns: lane pi holds
+  // st[I][j] = G[4I + pi][j], j = 0 .. 4I + 3, so that an elimination step's multipliers are the
+  // lane's own entries and only the pivot column's entries travel between lanes.
+  constexpr bool ROW = P == 4 && !BLK;
   const int lane = threadIdx.x & 63;
   const int pi = lane % P;  // position in the system's lane group
   const int qi = lane & 3;  // position in the quad (MFMA layout)
@@ -174,7 +180,11 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
         sfor<0, 4>([&](auto kk) {
           sfor<0, N>([&](auto I) {
             sfor<0, I + 1>([&](auto J) {
-              acc[tri(I, J)] = mfma4x4(a[I][(int)kk], a[J][(int)kk], acc[tri(I, J)]);
+              // row-owned layout: the transposed tile (lane q: row 4I + q, register v: column 4J + v)
+              if constexpr (ROW)
+                acc[tri(I, J)] = mfma4x4(a[J][(int)kk], a[I][(int)kk], acc[tri(I, J)]);
+              else
+                acc[tri(I, J)] = mfma4x4(a[I][(int)kk], a[J][(int)kk], acc[tri(I, J)]);
             });
           });
         });
@@ -224,7 +234,12 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
             float a[N];
             sfor<0, N>([&](auto J) { a[J] = Fr.row1(j, 4 * J + qi); });
             sfor<0, N>([&](auto I) {
-              sfor<0, I + 1>([&](auto J) { acc[tri(I, J)] = mfma4x4(a[I], a[J], acc[tri(I, J)]); });
+              sfor<0, I + 1>([&](auto J) {
+                if constexpr (ROW)
+                  acc[tri(I, J)] = mfma4x4(a[J], a[I], acc[tri(I, J)]);
+                else
+                  acc[tri(I, J)] = mfma4x4(a[I], a[J], acc[tri(I, J)]);
+              });
             });
             sfor<0, N>([&](auto J) { pb[J] = __builtin_fmaf(r, a[J], pb[J]); });
           }
@@ -239,7 +254,13 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
       const float dg = (!DUAL || c < cnt) ? reg : 1.0f;
       sfor<0, 4>([&](auto v) { acc[tri(J, J)][(int)v] += (qi == (int)v) ? dg : 0.f; });
     });
-    if constexpr (P == 4) {
+    if constexpr (ROW) {
+      sfor<0, N>([&](auto I) {
+        sfor<0, I + 1>([&](auto J) {
+          sfor<0, 4>([&](auto v) { st[I][4 * J + v] = acc[tri(I, J)][(int)v]; });
+        });
+      });
+    } else if constexpr (P == 4) {
       // the MFMA layout already is the owned-column layout
       sfor<0, M>([&](auto m) {
         sfor<0, D>([&](auto j) {
@@ -362,6 +383,51 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
         });
       }
     });
+  } else if constexpr (ROW) {
+    sfor<0, D>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value, mp = p / 4, pp = p % 4;
+      constexpr int m0 = pp == 3 ? mp + 1 : mp;  // first tile with rows below the pivot
+      const float d = quad_bcast_c<pp>(st[mp][p]);
+      bad |= !(d > 0.f);
+      const float s = __builtin_amdgcn_rcpf(d);
+      const float zp = quad_bcast_c<pp>(bm[mp]) * s;  // z_p = y_p / d_p
+      // the lane's rows c = 4I + pi below the pivot: G[c][p] (zero for c <= p), the forward
+      // substitution, and -L[c][p] = -G[c][p] / d_p kept in place for the back substitution
+      float gc[M];
+      sfor<m0, M>([&](auto Ii) {
+        constexpr int I = decltype(Ii)::value;
+        float v = st[I][p];
+        if constexpr (I == mp) v = pi > pp ? v : 0.f;
+        gc[I] = v;
+        bm[I] = __builtin_fmaf(-v, zp, bm[I]);
+        st[I][p] = -v * s;
+      });
+      bm[mp] = pi == pp ? zp : bm[mp];
+      // trailing update G[c][j] += G[c][p] (-G[j][p] / d_p) for c, j > p.  Tile column m0, which
+      // holds the next pivot's column, on the VALU: the factor of column j comes from row j's
+      // lane by DPP (rows of the diagonal tile above c are updated too, unused).
+      sfor<(p + 1 > 4 * m0 ? p + 1 : 4 * m0), 4 * m0 + 4>([&](auto Jj) {
+        constexpr int j = decltype(Jj)::value;
+        const float lj = quad_bcast_c<j % 4>(st[m0][p]);
+        sfor<m0, M>([&](auto Ii) {
+          constexpr int I = decltype(Ii)::value;
+          st[I][j] = __builtin_fmaf(gc[I], lj, st[I][j]);
+        });
+      });
+      // Later tile columns, needed a pivot or more later, as one rank-1 MFMA per tile (I, J):
+      // register v of lane q is G[4I + q][4J + v], so the A operand is the factor of rows
+      // 4J .. 4J + 3 (lane v's own st[J][p]) and the B operand the lane's gc[I].
+      sfor<m0 + 1, M>([&](auto Jj) {
+        constexpr int J = decltype(Jj)::value;
+        const float lJ = st[J][p];
+        sfor<J, M>([&](auto Ii) {
+          constexpr int I = decltype(Ii)::value;
+          f4 t = f4{st[I][4 * J], st[I][4 * J + 1], st[I][4 * J + 2], st[I][4 * J + 3]};
+          t = mfma4x4(lJ, gc[I], t);
+          sfor<0, 4>([&](auto v) { st[I][4 * J + v] = t[(int)v]; });
+        });
+      });
+    });
   } else {
     sfor<0, D>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
@@ -423,29 +489,54 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
   static_assert(!DUAL || KO % 4 == 0, "dual outputs are formed in 4-float chunks per lane");
   f4 u[DUAL ? KO / 4 : 1];
   if constexpr (DUAL) sfor<0, KO / 4>([&](auto c) { u[c] = f4{0.f, 0.f, 0.f, 0.f}; });
-  float dot[M];
-  sfor<0, M>([&](auto m) { dot[m] = 0.f; });
-  sfor_down<0, D>([&](auto Pp) {
-    constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
-    const float d = grp_bcast<P, pp>(st[mp][pp]);
-    const float xo = (bm[mp] - dot[mp]) * __builtin_amdgcn_rcpf(d);  // x_p in its owner lane
-    const float xp = grp_bcast<P, pp>(xo);
-    sfor<0, mp + 1>([&](auto Mm) {
-      constexpr int m = decltype(Mm)::value;
-      dot[m] = __builtin_fmaf(st[m][p - P * m], xp, dot[m]);  // row p of owned column P m + pi
+  if constexpr (ROW) {
+    // x_p = z_p - sum_{c > p} L[c][p] x_c: each lane sums over its solved rows (x = 0 until a
+    // row is solved), then the quad adds its four partial sums
+    float xv[M];
+    sfor<0, M>([&](auto m) { xv[m] = 0.f; });
+    sfor_down<0, D>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value, mp = p / 4, pp = p % 4;
+      float part = st[mp][p] * xv[mp];
+      sfor<mp + 1, M>([&](auto Ii) {
+        constexpr int I = decltype(Ii)::value;
+        part = __builtin_fmaf(st[I][p], xv[I], part);
+      });
+      part += quad_xor1(part);
+      part += quad_xor2(part);
+      const float xp = quad_bcast_c<pp>(bm[mp]) + part;
+      xv[mp] = pi == pp ? xp : xv[mp];
+      if constexpr (DUAL) {
+        const int j = ixs[sme * E + p];
+        sfor<0, KO / 4>([&](auto c) { u[c] += xp * Fr.row4(j, pi * KO + 4 * c); });
+        if constexpr (D >= 20) __builtin_amdgcn_sched_barrier(0);
+      }
     });
-    if constexpr (DUAL) {
-      const int j = ixs[sme * E + p];
-      sfor<0, KO / 4>([&](auto c) { u[c] += xp * Fr.row4(j, pi * KO + 4 * c); });
-      // keep the factor-row reads of later pivots from being hoisted here (register pressure)
-      if constexpr (D >= 20) __builtin_amdgcn_sched_barrier(0);
-    } else {
-      if constexpr (P == 1)
-        bm[mp] = xo;
-      else
-        bm[mp] = pi == pp ? xo : bm[mp];
-    }
-  });
+    if constexpr (!DUAL) sfor<0, M>([&](auto m) { bm[m] = xv[m]; });
+  } else {
+    float dot[M];
+    sfor<0, M>([&](auto m) { dot[m] = 0.f; });
+    sfor_down<0, D>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value, mp = p / P, pp = p % P;
+      const float d = grp_bcast<P, pp>(st[mp][pp]);
+      const float xo = (bm[mp] - dot[mp]) * __builtin_amdgcn_rcpf(d);  // x_p in its owner lane
+      const float xp = grp_bcast<P, pp>(xo);
+      sfor<0, mp + 1>([&](auto Mm) {
+        constexpr int m = decltype(Mm)::value;
+        dot[m] = __builtin_fmaf(st[m][p - P * m], xp, dot[m]);  // row p of owned column P m + pi
+      });
+      if constexpr (DUAL) {
+        const int j = ixs[sme * E + p];
+        sfor<0, KO / 4>([&](auto c) { u[c] += xp * Fr.row4(j, pi * KO + 4 * c); });
+        // keep the factor-row reads of later pivots from being hoisted here (register pressure)
+        if constexpr (D >= 20) __builtin_amdgcn_sched_barrier(0);
+      } else {
+        if constexpr (P == 1)
+          bm[mp] = xo;
+        else
+          bm[mp] = pi == pp ? xo : bm[mp];
+      }
+    });
+  }
 
   if constexpr (P == 2) my_flags |= __builtin_amdgcn_mov_dpp(my_flags, 0xb1, 0xf, 0xf, true);
   if constexpr (P == 4) {
