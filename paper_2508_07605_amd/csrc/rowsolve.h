@@ -406,14 +406,16 @@ __device__ __forceinline__ void solve_group(const FRows<K, LDSF> &Fr, int n, con
       // trailing update G[c][j] += G[c][p] (-G[j][p] / d_p) for c, j > p.  Tile column m0, which
       // holds the next pivot's column, on the VALU: the factor of column j comes from row j's
       // lane by DPP (rows of the diagonal tile above c are updated too, unused).
-      sfor<(p + 1 > 4 * m0 ? p + 1 : 4 * m0), 4 * m0 + 4>([&](auto Jj) {
-        constexpr int j = decltype(Jj)::value;
-        const float lj = quad_bcast_c<j % 4>(st[m0][p]);
-        sfor<m0, M>([&](auto Ii) {
-          constexpr int I = decltype(Ii)::value;
-          st[I][j] = __builtin_fmaf(gc[I], lj, st[I][j]);
+      if constexpr (m0 < M) {
+        sfor<(p + 1 > 4 * m0 ? p + 1 : 4 * m0), 4 * m0 + 4>([&](auto Jj) {
+          constexpr int j = decltype(Jj)::value;
+          const float lj = quad_bcast_c<j % 4>(st[m0][p]);
+          sfor<m0, M>([&](auto Ii) {
+            constexpr int I = decltype(Ii)::value;
+            st[I][j] = __builtin_fmaf(gc[I], lj, st[I][j]);
+          });
         });
-      });
+      }
       // Later tile columns, needed a pivot or more later, as one rank-1 MFMA per tile (I, J):
       // register v of lane q is G[4I + q][4J + v], so the A operand is the factor of rows
       // 4J .. 4J + 3 (lane v's own st[J][p]) and the B operand the lane's gc[I].
