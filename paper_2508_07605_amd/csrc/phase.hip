@@ -10,28 +10,39 @@
 // steps loaded ahead.  A ballot gives the step's "not below" mask; the run ending at each
 // lane is the distance to the last failing reading at or before it (or the carried run plus
 // the lane's position when there is none); a second ballot finds the first lane whose run
-// reaches N.  Reading stops at the report, so a trace costs 4 B per reading up to it.
+// reaches N, and the run carried to the next step is read from the step's last lane as a
+// scalar.  Reading stops at the report's block of eight steps.
 #include "common.h"
 
 namespace openk {
 
 constexpr int kPhaseAhead = 8;
 
+__device__ __forceinline__ int64_t readlane_i64(int64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __global__ __launch_bounds__(256) void k_phase_detect(const float *__restrict__ P, int64_t T, int64_t L, int64_t ld,
                                                       float th, int N, int64_t *__restrict__ first) {
   const int lane = threadIdx.x & 63;
+  // the wave's index as a scalar, so that the block's buffer resource stays in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t tr = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tr < T; tr += nw) {
+  for (int64_t tr = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv; tr < T; tr += nw) {
     const float *row = P + tr * ld;
     int64_t run = 0;  // readings not below the threshold ending just before the current step
     int64_t found = -1;
     for (int64_t base = 0; base < L && found < 0; base += 64 * kPhaseAhead) {
+      // the block through a buffer resource: readings past the trace read nothing, and no
+      // branch surrounds the loads
+      const int64_t rem = L - base;
+      const __amdgpu_buffer_rsrc_t rs =
+          make_rsrc(row + base, (uint64_t)(rem < 64 * kPhaseAhead ? rem : 64 * kPhaseAhead) * 4);
       float v[kPhaseAhead];
 #pragma unroll
-      for (int u = 0; u < kPhaseAhead; ++u) {
-        const int64_t i = base + 64 * u + lane;
-        v[u] = i < L ? row[i] : 0.f;
-      }
+      for (int u = 0; u < kPhaseAhead; ++u) v[u] = bload_f32(rs, (64 * u + lane) * 4);
 #pragma unroll
       for (int u = 0; u < kPhaseAhead; ++u) {
         const int64_t c0 = base + 64 * u;
@@ -47,7 +58,7 @@ __global__ __launch_bounds__(256) void k_phase_detect(const float *__restrict__ 
           found = c0 + __ffsll((long long)hit) - 1;
         } else {
           const int lastl = L - 1 - c0 < 63 ? (int)(L - 1 - c0) : 63;
-          run = __shfl(r, lastl, 64);
+          run = readlane_i64(r, lastl);  // lastl is wave-uniform
         }
       }
     }
