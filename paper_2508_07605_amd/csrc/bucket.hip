@@ -41,6 +41,8 @@ constexpr int kPasses = kRowsPerWave / kWave;
 
 // The rows of one wave (kPasses rows per lane, rows wbase + 64 p + lane): all row-pointer
 // loads are issued before any is used, so the latency is paid once rather than per pass.
+// They go through buffer resources over the wave's rows (nothing past the last row is read),
+// so no branch surrounds them.
 struct WaveRows {
   int c[kPasses];
   int64_t beg[kPasses];
@@ -49,21 +51,36 @@ struct WaveRows {
 __device__ __forceinline__ void load_wave_rows(WaveRows &r, int64_t m, const int64_t *__restrict__ ptr,
                                                const uint8_t *__restrict__ mask, int k, int64_t split_min,
                                                int64_t wbase, int lane) {
+  // wbase is the same in every lane; as a scalar it keeps the resources in scalar registers
+  const int64_t wb = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)((uint64_t)wbase >> 32)) << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wbase));
+  const int64_t left = m > wb ? m - wb : 0;
+  const int nr = (int)(left < kRowsPerWave ? left : kRowsPerWave);  // rows of the wave that exist
+  // first and one-past-last entry of each row through two resources with exact bounds (one
+  // 8-byte load each, none straddling a bound)
+  const int64_t *pb = ptr + (nr > 0 ? wb : 0);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(pb, (uint64_t)nr * 8), re = make_rsrc(pb + 1, (uint64_t)nr * 8);
   int64_t hi[kPasses];
-  uint8_t keep[kPasses];
+  int keep[kPasses];
 #pragma unroll
   for (int p = 0; p < kPasses; ++p) {
-    const int64_t i = wbase + p * kWave + lane;
-    const bool in = i < m;
-    r.beg[p] = in ? ptr[i] : 0;
-    hi[p] = in ? ptr[i + 1] : 0;
-    keep[p] = in ? (mask ? mask[i] : (uint8_t)1) : (uint8_t)0;
+    const int o = p * kWave + lane;
+    r.beg[p] = __builtin_bit_cast(int64_t, __builtin_amdgcn_raw_buffer_load_b64(rb, o * 8, 0, 0));
+    hi[p] = __builtin_bit_cast(int64_t, __builtin_amdgcn_raw_buffer_load_b64(re, o * 8, 0, 0));
+  }
+  if (mask) {
+    const __amdgpu_buffer_rsrc_t rm = make_rsrc(mask + (nr > 0 ? wb : 0), (uint64_t)nr);
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) keep[p] = __builtin_amdgcn_raw_buffer_load_b8(rm, p * kWave + lane, 0, 0);
+  } else {
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) keep[p] = p * kWave + lane < nr;
   }
 #pragma unroll
   for (int p = 0; p < kPasses; ++p) {
     const int64_t n = hi[p] - r.beg[p];
     r.cnt[p] = (int)n;
-    r.c[p] = keep[p] ? row_class(n, k, split_min) : -1;
+    r.c[p] = (keep[p] && p * kWave + lane < nr) ? row_class(n, k, split_min) : -1;
   }
 }
 
