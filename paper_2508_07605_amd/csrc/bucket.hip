@@ -47,10 +47,12 @@ struct WaveRows {
   int c[kPasses];
   int64_t beg[kPasses];
   int cnt[kPasses];
+  int64_t end[kPasses];  // one past the row's last entry (while loading)
+  int keep[kPasses];     // row exists and is not masked out (while loading)
 };
-__device__ __forceinline__ void load_wave_rows(WaveRows &r, int64_t m, const int64_t *__restrict__ ptr,
-                                               const uint8_t *__restrict__ mask, int k, int64_t split_min,
-                                               int64_t wbase, int lane) {
+// issues the loads only; wave_rows_classify uses them
+__device__ __forceinline__ void wave_rows_issue(WaveRows &r, int64_t m, const int64_t *__restrict__ ptr,
+                                                const uint8_t *__restrict__ mask, int64_t wbase, int lane) {
   // wbase is the same in every lane; as a scalar it keeps the resources in scalar registers
   const int64_t wb = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)((uint64_t)wbase >> 32)) << 32) |
                                (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wbase));
@@ -60,28 +62,34 @@ __device__ __forceinline__ void load_wave_rows(WaveRows &r, int64_t m, const int
   // 8-byte load each, none straddling a bound)
   const int64_t *pb = ptr + (nr > 0 ? wb : 0);
   const __amdgpu_buffer_rsrc_t rb = make_rsrc(pb, (uint64_t)nr * 8), re = make_rsrc(pb + 1, (uint64_t)nr * 8);
-  int64_t hi[kPasses];
-  int keep[kPasses];
 #pragma unroll
   for (int p = 0; p < kPasses; ++p) {
     const int o = p * kWave + lane;
     r.beg[p] = __builtin_bit_cast(int64_t, __builtin_amdgcn_raw_buffer_load_b64(rb, o * 8, 0, 0));
-    hi[p] = __builtin_bit_cast(int64_t, __builtin_amdgcn_raw_buffer_load_b64(re, o * 8, 0, 0));
+    r.end[p] = __builtin_bit_cast(int64_t, __builtin_amdgcn_raw_buffer_load_b64(re, o * 8, 0, 0));
   }
   if (mask) {
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(mask + (nr > 0 ? wb : 0), (uint64_t)nr);
 #pragma unroll
-    for (int p = 0; p < kPasses; ++p) keep[p] = __builtin_amdgcn_raw_buffer_load_b8(rm, p * kWave + lane, 0, 0);
+    for (int p = 0; p < kPasses; ++p) r.keep[p] = __builtin_amdgcn_raw_buffer_load_b8(rm, p * kWave + lane, 0, 0);
   } else {
 #pragma unroll
-    for (int p = 0; p < kPasses; ++p) keep[p] = p * kWave + lane < nr;
+    for (int p = 0; p < kPasses; ++p) r.keep[p] = p * kWave + lane < nr;
   }
+}
+__device__ __forceinline__ void wave_rows_classify(WaveRows &r, int k, int64_t split_min) {
 #pragma unroll
   for (int p = 0; p < kPasses; ++p) {
-    const int64_t n = hi[p] - r.beg[p];
+    const int64_t n = r.end[p] - r.beg[p];
     r.cnt[p] = (int)n;
-    r.c[p] = (keep[p] && p * kWave + lane < nr) ? row_class(n, k, split_min) : -1;
+    r.c[p] = r.keep[p] ? row_class(n, k, split_min) : -1;
   }
+}
+__device__ __forceinline__ void load_wave_rows(WaveRows &r, int64_t m, const int64_t *__restrict__ ptr,
+                                               const uint8_t *__restrict__ mask, int k, int64_t split_min,
+                                               int64_t wbase, int lane) {
+  wave_rows_issue(r, m, ptr, mask, wbase, lane);
+  wave_rows_classify(r, k, split_min);
 }
 
 // the classes that occur among the wave's rows, as a bit set (the same value in every lane)
@@ -194,19 +202,38 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
   __shared__ int wcnt[kBucketThreads / kWave][kNumClasses];
   __shared__ int run[kNumClasses];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // the wave's rows first: their loads are in flight while the block derives its offsets
+  const int64_t wbase = (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)w * kRowsPerWave;
+  WaveRows r;
+  wave_rows_issue(r, m, ptr, mask, wbase, lane);
   if constexpr (SELF_SCAN) {
     __shared__ int tot[kNumClasses], pre[kNumClasses];
     const int nblk = (int)gridDim.x, me = (int)blockIdx.x;
-    for (int c = w; c < kNumClasses; c += kBucketThreads / kWave) {
+    // wave w sums classes w, w + 8, w + 16: every count it needs is loaded before any is added
+    // (one round trip to L2 instead of one per class and per 64 blocks)
+    constexpr int WV = kBucketThreads / kWave, CW = (kNumClasses + WV - 1) / WV, BL = kSelfScanMaxBlocks / kWave;
+    const __amdgpu_buffer_rsrc_t ro = make_rsrc(offs, (uint64_t)kNumClasses * nblk * sizeof(int32_t));
+    int h[CW][BL];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int c = w + WV * j < kNumClasses ? w + WV * j : kNumClasses - 1;
+#pragma unroll
+      for (int i = 0; i < BL; ++i) h[j][i] = bload_i32(ro, (c * nblk + lane + kWave * i) * (int)sizeof(int32_t));
+    }
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+      const int c = w + WV * j;
       int t = 0, p = 0;
-      for (int b = lane; b < nblk; b += kWave) {
-        const int h = offs[(int64_t)c * nblk + b];
-        t += h;
-        p += b < me ? h : 0;
+#pragma unroll
+      for (int i = 0; i < BL; ++i) {
+        const int b = lane + kWave * i;
+        const int x = b < nblk ? h[j][i] : 0;
+        t += x;
+        p += b < me ? x : 0;
       }
       t = wave_sum_i(t);
       p = wave_sum_i(p);
-      if (lane == 0) {
+      if (lane == 0 && c < kNumClasses) {
         tot[c] = t;
         pre[c] = p;
       }
@@ -226,9 +253,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_class_place(int64_t m, const
   }
   // Each wave places its own contiguous rows: first its per-class counts (lane cc holds class
   // cc), then, from its start within the block's run, the rows in order with ballot ranks.
-  const int64_t wbase = (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)w * kRowsPerWave;
-  WaveRows r;
-  load_wave_rows(r, m, ptr, mask, k, split_min, wbase, lane);
+  wave_rows_classify(r, k, split_min);
   const unsigned present = wave_classes_present(r);
   const int mine = wave_class_counts(r, lane, present);
   if (lane < kNumClasses) wcnt[w][lane] = mine;
