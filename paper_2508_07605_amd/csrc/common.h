@@ -74,6 +74,13 @@ __device__ __forceinline__ f4 mfma4x4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
+// lane l's value of a 64-bit per-lane quantity (l wave-uniform)
+__device__ __forceinline__ int64_t readlane_i64(int64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int wave_max_i(int x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {

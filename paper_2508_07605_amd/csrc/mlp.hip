@@ -543,12 +543,6 @@ constexpr int kHP = 256 + 8;  // LDS pitch of an activation row (bf16)
 constexpr int kCap = 176;     // entries staged per wavefront (three blocks per CU up to rank 32)
 static_assert(kCap % 8 == 0, "a staged chunk is padded to a multiple of eight entries");
 
-__device__ __forceinline__ int64_t readlane_i64(int64_t x, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 template <int K>
 __global__ __launch_bounds__(256, 3) void k_mlp_infer(int64_t m, const int64_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col, const float *__restrict__ val,

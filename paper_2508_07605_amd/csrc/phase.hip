@@ -18,12 +18,6 @@ namespace openk {
 
 constexpr int kPhaseAhead = 8;
 
-__device__ __forceinline__ int64_t readlane_i64(int64_t x, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 __global__ __launch_bounds__(256) void k_phase_detect(const float *__restrict__ P, int64_t T, int64_t L, int64_t ld,
                                                       float th, int N, int64_t *__restrict__ first) {
   const int lane = threadIdx.x & 63;
