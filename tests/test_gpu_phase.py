@@ -57,6 +57,19 @@ def test_edges(ctx):
     assert empty.numel() == 0
 
 
+def test_row_stride_through_the_c_abi(ctx):
+    # traces of L readings at a row stride ld > L (the binding passes contiguous rows only)
+    r = np.random.default_rng(11)
+    T, L, ld = 50, 777, 777 + 37
+    wide = r.choice(np.array([10.0, 60.0, 150.0], np.float32), size=(T, ld), p=[0.01, 0.3, 0.69])
+    dev = torch.from_numpy(wide).cuda()
+    out = torch.empty(T, dtype=torch.int64, device="cuda")
+    ctx.check(native.lib().open_phase_detect(ctx.handle, dev.data_ptr(), T, L, ld, 60.0, 25, out.data_ptr()))
+    torch.cuda.synchronize()
+    want = np.array([phase.detect(tr[:L]) for tr in wide])
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
 def test_rejects_bad_arguments(ctx):
     P = torch.ones((2, 10), dtype=torch.float32, device="cuda")
     with pytest.raises(native.OpenError):
